@@ -1,0 +1,120 @@
+"""Algorithm 1, GPU version (sec. 2.5): n candidates per iteration, argmin of
+the path length over the non-discarded ones, reconstruction of the winner from
+its random draw, update of x* and x_old.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Readings (listed in the design doc): Step 4 evaluates the initial x with the gate
+off and keeps its minimised units; a candidate starts from the units of its
+base; x* is replaced only on a strict decrease of C (and then T* becomes the
+winner's makespan); when every candidate is discarded x_old becomes the base;
+the improvement indicator is 1 or 2 when x* improved through a field or a BP
+move (Fig. 3 caption), else 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+from . import model as M
+from .moves import FIELD, Move, apply_move, draw_move, exploit_draw, is_valid
+
+
+@dataclasses.dataclass
+class CandidateResult:
+    key: int
+    cost_km: float
+    makespan_s: float
+    flags: int
+    evaluation: Optional[M.Evaluation]
+
+
+def evaluate_move(inst, base: M.Solution, mv: Move, index: int, gate: str, t_star,
+                  caps=None, embedded_min: bool = True) -> CandidateResult:
+    if not is_valid(inst, base, mv):
+        return CandidateResult(M.INF_KEY, M.INF, M.INF, M.FLAG_INVALID, None)
+    ev = M.evaluate_solution(inst, apply_move(base, mv), caps, embedded_min)
+    if not ev.feasible:
+        return CandidateResult(M.INF_KEY, M.INF, M.INF, ev.flags, ev)
+    return CandidateResult(M.candidate_key(ev, index, gate, t_star), ev.cost_km, ev.makespan_s,
+                           M.candidate_flags(ev, gate, t_star), ev)
+
+
+@dataclasses.dataclass
+class TraceRow:
+    it: int
+    use_best: bool
+    best_key: int
+    cost_m: int          # C* after the iteration
+    makespan_s: float    # T* after the iteration
+    indicator: int       # 0, 1 (field move improved x*), 2 (BP move improved x*)
+
+
+@dataclasses.dataclass
+class SearchState:
+    it: int
+    x_best: M.Solution
+    cost_best: int
+    t_best: float
+    x_old: M.Solution
+    trace: List[TraceRow]
+
+
+def with_units(sol: M.Solution, ev: M.Evaluation) -> M.Solution:
+    out = sol.copy()
+    out.hu_tour = list(ev.hu_tour)
+    out.su_tour = list(ev.su_tour)
+    return out
+
+
+def start(inst, x0: M.Solution, caps=None, embedded_min: bool = True) -> SearchState:
+    """Step 4: summarise the initial solution as x*, cost it, x_old = x*."""
+    ev = M.evaluate_solution(inst, x0, caps, embedded_min)
+    assert ev.feasible
+    xb = with_units(x0, ev)
+    return SearchState(0, xb, ev.cost_m, ev.makespan_s, xb.copy(), [])
+
+
+def step(inst, st: SearchState, seed: int, n: int, eps_threshold: int, gate: str = M.GATE_LE,
+         inst_idx: int = 0, fixed_field_bp: bool = False, caps=None,
+         embedded_min: bool = True) -> SearchState:
+    """One iteration of the loop of Algorithm 1 (GPU version)."""
+    it = st.it
+    use_best = exploit_draw(seed, it, inst_idx, eps_threshold)
+    base = st.x_best if use_best else st.x_old
+    best = None
+    best_key = M.INF_KEY
+    for i in range(n):
+        mv = draw_move(inst, base, seed, it, i, inst_idx, fixed_field_bp)
+        r = evaluate_move(inst, base, mv, i, gate, st.t_best, caps, embedded_min)
+        if r.key < best_key:
+            best_key, best = r.key, (mv, r)
+    indicator = 0
+    if best is None:
+        x_old = base
+        xb, cb, tb = st.x_best, st.cost_best, st.t_best
+    else:
+        mv, r = best
+        x_new = with_units(apply_move(base, mv), r.evaluation)
+        xb, cb, tb = st.x_best, st.cost_best, st.t_best
+        if r.evaluation.cost_m < st.cost_best:
+            xb, cb, tb = x_new, r.evaluation.cost_m, r.evaluation.makespan_s
+            indicator = 1 if mv.kind == FIELD else 2
+        x_old = x_new
+    trace = st.trace + [TraceRow(it, use_best, best_key, cb, tb, indicator)]
+    return SearchState(it + 1, xb, cb, tb, x_old, trace)
+
+
+def search(inst, x0: M.Solution, seed: int, n: int, iters: int, eps_threshold: int,
+           gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
+           caps=None, embedded_min: bool = True) -> SearchState:
+    st = start(inst, x0, caps, embedded_min)
+    for _ in range(iters):
+        st = step(inst, st, seed, n, eps_threshold, gate, inst_idx, fixed_field_bp, caps,
+                  embedded_min)
+    return st
+
+
+def eps_threshold(eps: float) -> int:
+    """floor(eps * 2^32), in [0, 2^32]."""
+    return int(eps * (1 << 32))
