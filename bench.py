@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the device-resident search iteration (Algorithm 1, GPU
+version): candidate evaluations per second on one MI355X.
+
+A step is one full iteration on the device: eq. (6) base pick, n candidates
+drawn (Philox) and evaluated (walk, eq. (2), HU and SU rebalancing, cost,
+gate), argmin, reconstruction and commit of the winner.  Inputs are seeded
+synthetic instances resident in HBM before the timed region.
+
+Prints one JSON line.  The roofline object prices the evaluation kernel's
+algorithmic LDS bytes per candidate (the full walk) against the LDS peak;
+the cpu_baseline object times the CPU oracle on a bounded sample of the same
+iteration's candidates.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+
+DESCR = {
+    "tiny12": "12 fields, 3 BPs, 2 tours, 4 HUs, 8 SUs, 50 km square",
+    "mid100": "100 fields, 10 BPs, 5 tours, 12 HUs, 40 SUs, 100 km square",
+    "clust500": "500 fields in 20 clusters, 20 BPs, 10 tours, 30 HUs, 120 SUs, 200 km square",
+}
+
+
+def lds_bytes_per_candidate(nf, nb, nt, nhu, nsu):
+    """Algorithmic LDS bytes of one full evaluation: per field visited 22 B
+    (position 2, successor leg 4, field-BP distance 4, area 4, supply 4,
+    shuttle drives 4), per BP 12 B (list entry 2, start 2, length 2, demand 4,
+    tour offset 2), per tour 28 B (offsets 4, unit masks 24) and 4 B per unit
+    (rate or fill time)."""
+    return 22 * nf + 12 * nb + 28 * nt + 4 * (nhu + nsu)
+
+
+def cpu_baseline(inst, x0, n_sample):
+    from oracle import search as S
+    from tests.oracle_pool import OraclePool, n_procs
+    st = S.start(inst, x0)
+    thr = S.eps_threshold(0.5)
+    from oracle.moves import exploit_draw
+    base = st.x_best if exploit_draw(0, 0, 0, thr) else st.x_old
+    job = (inst, base, 0, 0, 0, False, "le", st.t_best, None, True)
+    procs = n_procs()
+    pool = OraclePool(procs)
+    pool(job, procs)  # start the workers outside the timed region
+    t0 = time.perf_counter()
+    pool(job, n_sample)
+    dt = time.perf_counter() - t0
+    pool.close()
+    return dict(value=n_sample / dt, unit="evals/s", cores=procs, kind="oracle",
+                sample="first %d candidates of iteration 0 (seed 0, eps 0.5), %d processes, %.1f s"
+                % (n_sample, procs, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="mid100", choices=sorted(DESCR))
+    ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 14)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1909_10286_amd import bl, inputs
+
+    wl = inputs.WORKLOADS[a.workload]
+    n = a.n or wl["n_cand"]
+    ctx = bl.Context(0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream)
+
+    def accept(inst):
+        iid = ctx.instance_upload(inst)
+        try:
+            ctx.init_solution(iid)
+            return True
+        except bl.BlError as e:
+            if e.status == bl.EINFEASIBLE:
+                return False
+            raise
+    inst = inputs.make_instance(a.workload, 0, accept=accept)
+    iid = ctx.instance_upload(inst)
+    x0 = ctx.init_solution(iid)
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, a.warmup + a.steps)
+    seed, thr = 0, 1 << 31  # eps = 0.5
+    for _ in range(a.warmup):
+        ctx.search_step(iid, seed, thr, n)
+    torch.cuda.synchronize()
+    ctx.timing_read()
+    ctx.timing_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.search_step(iid, seed, thr, n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    eval_ms, launches = ctx.timing_read()
+    ctx.timing_enable(False)
+    state = ctx.search_state(iid)
+    secs = ms / 1e3
+    value = n * a.steps / secs
+    per_launch_s = eval_ms / 1e3 / max(launches, 1)
+    bpc = lds_bytes_per_candidate(inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus)
+    achieved = bpc * n / per_launch_s / 1e9
+    out = {
+        "metric": "candidate evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s, %d candidates/iteration" % (a.workload, DESCR[a.workload], n),
+                   "n_candidates": n, "instance_seed": 0, "search_seed": seed, "eps": 0.5,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "kernel": "k_eval (search mode)", "bytes_per_candidate": bpc,
+                     "kernel_ms_per_launch": per_launch_s * 1e3},
+        "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,
+                   "iterations": state["it"], "wall_s": wall},
+    }
+    if not a.no_cpu_baseline:
+        from oracle import init as OI
+        from tests.gpu_common import from_csr
+        out["cpu_baseline"] = cpu_baseline(inst, from_csr(x0), a.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,20 +75,34 @@ def start(inst, x0: M.Solution, caps=None, embedded_min: bool = True) -> SearchS
     return SearchState(0, xb, ev.cost_m, ev.makespan_s, xb.copy(), [])
 
 
+def candidate(job, i):
+    """Key and result of candidate i of one iteration (job = the iteration's
+    fixed arguments)."""
+    inst, base, seed, it, inst_idx, fixed_field_bp, gate, t_star, caps, embedded_min = job
+    mv = draw_move(inst, base, seed, it, i, inst_idx, fixed_field_bp)
+    r = evaluate_move(inst, base, mv, i, gate, t_star, caps, embedded_min)
+    return r.key, r
+
+
 def step(inst, st: SearchState, seed: int, n: int, eps_threshold: int, gate: str = M.GATE_LE,
          inst_idx: int = 0, fixed_field_bp: bool = False, caps=None,
-         embedded_min: bool = True) -> SearchState:
-    """One iteration of the loop of Algorithm 1 (GPU version)."""
+         embedded_min: bool = True, map_fn=None) -> SearchState:
+    """One iteration of the loop of Algorithm 1 (GPU version).  ``map_fn(job,
+    n)`` may return the n candidate keys computed elsewhere (e.g. by a process
+    pool running ``candidate``); by default they are computed in turn."""
     it = st.it
     use_best = exploit_draw(seed, it, inst_idx, eps_threshold)
     base = st.x_best if use_best else st.x_old
     best = None
     best_key = M.INF_KEY
-    for i in range(n):
-        mv = draw_move(inst, base, seed, it, i, inst_idx, fixed_field_bp)
-        r = evaluate_move(inst, base, mv, i, gate, st.t_best, caps, embedded_min)
-        if r.key < best_key:
-            best_key, best = r.key, (mv, r)
+    job = (inst, base, seed, it, inst_idx, fixed_field_bp, gate, st.t_best, caps, embedded_min)
+    keys = map_fn(job, n) if map_fn is not None else [candidate(job, i)[0] for i in range(n)]
+    for i, k in enumerate(keys):
+        if k < best_key:
+            best_key, best = k, i
+    if best is not None:
+        mv = draw_move(inst, base, seed, it, best, inst_idx, fixed_field_bp)
+        best = (mv, evaluate_move(inst, base, mv, best, gate, st.t_best, caps, embedded_min))
     indicator = 0
     if best is None:
         x_old = base
@@ -107,11 +121,11 @@ def step(inst, st: SearchState, seed: int, n: int, eps_threshold: int, gate: str
 
 def search(inst, x0: M.Solution, seed: int, n: int, iters: int, eps_threshold: int,
            gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
-           caps=None, embedded_min: bool = True) -> SearchState:
+           caps=None, embedded_min: bool = True, map_fn=None) -> SearchState:
     st = start(inst, x0, caps, embedded_min)
     for _ in range(iters):
         st = step(inst, st, seed, n, eps_threshold, gate, inst_idx, fixed_field_bp, caps,
-                  embedded_min)
+                  embedded_min, map_fn)
     return st
 
 

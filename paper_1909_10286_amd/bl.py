@@ -1,0 +1,275 @@
+"""ctypes binding of libbl.so (include/bl.h), argument marshalling only.
+
+Every step of the evaluation runs in the library's HIP kernels; PyTorch only
+provides device buffers (``tensor.data_ptr()``) and the stream.  Loading fails
+loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbl.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EINFEASIBLE = 0, -1, -2, -3, -4, -5
+FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT = 1, 2, 4, 8
+CAND_INFEASIBLE, CAND_GATED, CAND_CAP_HU, CAND_CAP_SU, CAND_INVALID, CAND_INF_MAKESPAN = (
+    1, 2, 4, 8, 16, 32)
+SLOT_BASE, SLOT_BEST, SLOT_OLD = 0, 1, 2
+INF_KEY = (1 << 64) - 1
+INF_MAKESPAN = 0x7FFFFFFF
+
+_u32p = C.POINTER(C.c_uint32)
+_u16p = C.POINTER(C.c_uint16)
+_i32p = C.POINTER(C.c_int32)
+
+
+class _Instance(C.Structure):
+    _fields_ = [("n_fields", C.c_int32), ("n_bps", C.c_int32), ("n_tours", C.c_int32),
+                ("n_hus", C.c_int32), ("n_sus", C.c_int32),
+                ("dist_m", _u32p), ("field_area", _u32p), ("field_yield", _u32p),
+                ("bp_demand_kg", _u32p), ("hu_rate", _u32p), ("hu_speed_mph", C.c_uint32),
+                ("su_cap_kg", _u32p), ("su_speed_mph", _u32p), ("su_fill_s", _u32p),
+                ("xy_m", _i32p), ("init_hus_per_tour", _u16p), ("init_sus_per_tour", _u16p),
+                ("flags", C.c_uint32), ("cap_hu", C.c_uint32), ("cap_su", C.c_uint32)]
+
+
+class _Solution(C.Structure):
+    _fields_ = [("tour_off", _u16p), ("tour_bp", _u16p), ("bp_off", _u16p),
+                ("bp_field", _u16p), ("hu_tour", _u16p), ("su_tour", _u16p)]
+
+
+class _SearchParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("eps_threshold", C.c_uint64), ("n", C.c_uint32),
+                ("inst_index", C.c_uint32)]
+
+
+class _SearchState(C.Structure):
+    _fields_ = [("it", C.c_uint32), ("n_improved", C.c_uint32), ("cost_best_m", C.c_uint64),
+                ("t_best_s", C.c_int64)]
+
+
+class _TraceRow(C.Structure):
+    _fields_ = [("best_key", C.c_uint64), ("cost_m", C.c_uint64), ("makespan_s", C.c_int64),
+                ("it", C.c_uint32), ("indicator", C.c_uint8), ("use_best", C.c_uint8),
+                ("pad", C.c_uint8 * 2)]
+
+
+_SIGS = {
+    "bl_create": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p)]),
+    "bl_destroy": (None, [C.c_void_p]),
+    "bl_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "bl_status_str": (C.c_char_p, [C.c_int32]),
+    "bl_last_error": (C.c_char_p, [C.c_void_p]),
+    "bl_instance_upload": (C.c_int32, [C.c_void_p, C.POINTER(_Instance), C.POINTER(C.c_int32)]),
+    "bl_init_solution": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_Solution)]),
+    "bl_solution_upload": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]),
+    "bl_solution_download": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]),
+    "bl_generate": (C.c_int32, [C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                C.c_uint32, C.c_uint32, C.c_void_p]),
+    "bl_evaluate_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint32, C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bl_select_best": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "bl_search_start": (C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32]),
+    "bl_search_step": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams)]),
+    "bl_search_state_get": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchState)]),
+    "bl_search_trace": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_TraceRow), C.c_uint32,
+                                    C.POINTER(C.c_uint32)]),
+    "bl_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "bl_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint32)]),
+}
+
+EXPORTED = sorted(_SIGS)
+_lib: Optional[C.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libbl.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libbl.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class BlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (load().bl_status_str(status).decode(), status, msg))
+        self.status = status
+
+
+@dataclasses.dataclass
+class CSR:
+    """Solution in the library's compressed-list layout (numpy uint16)."""
+    tour_off: np.ndarray
+    tour_bp: np.ndarray
+    bp_off: np.ndarray
+    bp_field: np.ndarray
+    hu_tour: np.ndarray
+    su_tour: np.ndarray
+
+    @staticmethod
+    def empty(nf, nb, nt, nhu, nsu) -> "CSR":
+        z = lambda n: np.zeros(n, dtype=np.uint16)
+        return CSR(z(nt + 1), z(nb), z(nb + 1), z(nf), z(nhu), z(nsu))
+
+    @staticmethod
+    def from_lists(tours: List[List[int]], fields: List[List[int]], hu_tour, su_tour) -> "CSR":
+        toff = np.cumsum([0] + [len(t) for t in tours]).astype(np.uint16)
+        boff = np.cumsum([0] + [len(f) for f in fields]).astype(np.uint16)
+        cat = lambda xs: np.asarray([v for x in xs for v in x], dtype=np.uint16)
+        return CSR(toff, cat(tours), boff, cat(fields), np.asarray(hu_tour, np.uint16),
+                   np.asarray(su_tour, np.uint16))
+
+    def to_lists(self):
+        t = [list(map(int, self.tour_bp[self.tour_off[g]:self.tour_off[g + 1]]))
+             for g in range(len(self.tour_off) - 1)]
+        f = [list(map(int, self.bp_field[self.bp_off[b]:self.bp_off[b + 1]]))
+             for b in range(len(self.bp_off) - 1)]
+        return t, f, list(map(int, self.hu_tour)), list(map(int, self.su_tour))
+
+    def _struct(self) -> _Solution:
+        for a in (self.tour_off, self.tour_bp, self.bp_off, self.bp_field, self.hu_tour, self.su_tour):
+            assert a.dtype == np.uint16 and a.flags.c_contiguous
+        p = lambda a: a.ctypes.data_as(_u16p)
+        return _Solution(p(self.tour_off), p(self.tour_bp), p(self.bp_off), p(self.bp_field),
+                         p(self.hu_tour), p(self.su_tour))
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (or an int already), or NULL."""
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+class Context:
+    """One library context on one GPU.  Methods mirror the C calls."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = C.c_void_p()
+        st = self._lib.bl_create(device, C.byref(h))
+        if st != OK:
+            raise BlError(st, "bl_create(%d)" % device)
+        self._h = h
+        self._sizes = {}
+
+    def close(self):
+        if self._h:
+            self._lib.bl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            raise BlError(st, self._lib.bl_last_error(self._h).decode())
+
+    def set_stream(self, stream):
+        """stream: torch.cuda.Stream, a raw hipStream_t int, or None (default)."""
+        raw = 0 if stream is None else (stream if isinstance(stream, int) else stream.cuda_stream)
+        self._check(self._lib.bl_set_stream(self._h, C.c_void_p(raw)))
+
+    def instance_upload(self, inst, flags: int = 0, cap_hu: int = 0, cap_su: int = 0) -> int:
+        keep = []
+
+        def u32(a):
+            a = np.ascontiguousarray(a, dtype=np.uint32)
+            keep.append(a)
+            return a.ctypes.data_as(_u32p)
+
+        def u16(a):
+            if a is None:
+                return C.cast(None, _u16p)
+            a = np.ascontiguousarray(a, dtype=np.uint16)
+            keep.append(a)
+            return a.ctypes.data_as(_u16p)
+        xy = np.ascontiguousarray(np.asarray(inst.xy_m).reshape(-1), dtype=np.int32)
+        keep.append(xy)
+        s = _Instance(inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus,
+                      u32(inst.dist_m), u32(inst.field_area), u32(inst.field_yield),
+                      u32(inst.bp_demand_kg), u32(inst.hu_rate), int(inst.hu_speed_mph),
+                      u32(inst.su_cap_kg), u32(inst.su_speed_mph), u32(inst.su_fill_s),
+                      xy.ctypes.data_as(_i32p), u16(inst.init_hus_per_tour),
+                      u16(inst.init_sus_per_tour), flags, cap_hu, cap_su)
+        out = C.c_int32()
+        self._check(self._lib.bl_instance_upload(self._h, C.byref(s), C.byref(out)))
+        self._sizes[out.value] = (inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus)
+        return out.value
+
+    def init_solution(self, inst_id: int) -> CSR:
+        sol = CSR.empty(*self._sizes[inst_id])
+        self._check(self._lib.bl_init_solution(self._h, inst_id, C.byref(sol._struct())))
+        return sol
+
+    def solution_upload(self, inst_id: int, slot: int, sol: CSR):
+        self._check(self._lib.bl_solution_upload(self._h, inst_id, slot, C.byref(sol._struct())))
+
+    def solution_download(self, inst_id: int, slot: int) -> CSR:
+        sol = CSR.empty(*self._sizes[inst_id])
+        self._check(self._lib.bl_solution_download(self._h, inst_id, slot, C.byref(sol._struct())))
+        return sol
+
+    def generate(self, inst_id, seed, it, inst_index, first, n, d_moves):
+        self._check(self._lib.bl_generate(self._h, inst_id, seed, it, inst_index, first, n,
+                                          C.c_void_p(_ptr(d_moves))))
+
+    def evaluate_batch(self, inst_id, d_moves, n, t_star_s, d_key, d_cost=None, d_makespan=None,
+                       d_flags=None):
+        self._check(self._lib.bl_evaluate_batch(
+            self._h, inst_id, C.c_void_p(_ptr(d_moves)), n, int(t_star_s),
+            C.c_void_p(_ptr(d_key)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_makespan)),
+            C.c_void_p(_ptr(d_flags))))
+
+    def select_best(self, d_key, n, d_best):
+        self._check(self._lib.bl_select_best(self._h, C.c_void_p(_ptr(d_key)), n,
+                                             C.c_void_p(_ptr(d_best))))
+
+    def search_start(self, inst_id: int, trace_capacity: int = 0):
+        self._check(self._lib.bl_search_start(self._h, inst_id, trace_capacity))
+
+    def search_step(self, inst_id: int, seed: int, eps_threshold: int, n: int, inst_index: int = 0):
+        p = _SearchParams(seed, eps_threshold, n, inst_index)
+        self._check(self._lib.bl_search_step(self._h, inst_id, C.byref(p)))
+
+    def search_state(self, inst_id: int) -> dict:
+        s = _SearchState()
+        self._check(self._lib.bl_search_state_get(self._h, inst_id, C.byref(s)))
+        return dict(it=s.it, n_improved=s.n_improved, cost_best_m=s.cost_best_m, t_best_s=s.t_best_s)
+
+    def search_trace(self, inst_id: int, max_rows: int = 1 << 20) -> list:
+        st = self.search_state(inst_id)
+        rows = min(max_rows, st["it"])
+        buf = (_TraceRow * max(rows, 1))()
+        got = C.c_uint32()
+        self._check(self._lib.bl_search_trace(self._h, inst_id, buf, rows, C.byref(got)))
+        return [dict(best_key=r.best_key, cost_m=r.cost_m, makespan_s=r.makespan_s, it=r.it,
+                     indicator=r.indicator, use_best=r.use_best) for r in buf[:got.value]]
+
+    def timing_enable(self, on: bool = True):
+        self._check(self._lib.bl_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        """(summed evaluation-kernel ms, launches) since the last read."""
+        ms, n = C.c_double(), C.c_uint32()
+        self._check(self._lib.bl_timing_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,112 @@
+// Internal layout shared by the host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bl {
+
+constexpr int kMaxFields = 32767;
+constexpr int kMaxBps = 4096;
+constexpr int kMaxTours = 64;
+constexpr int kMaxHus = 64;
+constexpr int kMaxSus = 128;
+constexpr uint32_t kMaxCand = 1u << 24;
+
+constexpr uint64_t kInfKey = ~0ull;
+constexpr int64_t kInfT = INT64_MAX;
+constexpr int64_t kNegInfT = INT64_MIN;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8 };
+enum : uint32_t {
+  kCandInfeasible = 1, kCandGated = 2, kCandCapHu = 4, kCandCapSu = 8, kCandInvalid = 16,
+  kCandInfMakespan = 32
+};
+
+// Word offsets (32-bit words) of the arrays of the per-instance image.  The
+// image is one contiguous buffer that every evaluating workgroup copies into
+// LDS unchanged.  The first `static_words` words never change after upload;
+// the rest (the base view) is rewritten whenever the base solution changes.
+struct ImageLayout {
+  // static, per field id: area (0.01 ha), supply (kg), shuttle drives, D[HQ][f]
+  uint32_t area, supply, nsh, dhq;
+  uint32_t demand;                          // per BP, kg
+  uint32_t hu_rate, su_fill, su_speed;      // per unit rank
+  uint32_t hu_rank, su_rank;                // u16 per unit id -> rank
+  // base view
+  uint32_t seq;       // u16 per position: field at that position of the base
+  uint32_t pos;       // u16 per field: its position
+  uint32_t fbp;       // u16 per field: its BP
+  uint32_t fidx;      // u16 per field: its index in the BP's list
+  uint32_t leg_in;    // u32 per position q: D[field(q-1)][field(q)], q=0: D[HQ][field(0)]
+  uint32_t dfb;       // u32 per position: D[field][its BP]
+  uint32_t bp_start;  // u16 per BP: position of its first field
+  uint32_t bp_len;    // u16 per BP: number of fields
+  uint32_t bp_tour;   // u16 per BP: its tour
+  uint32_t bp_idx;    // u16 per BP: its index in the tour's list
+  uint32_t tour_off;  // u16 [NT+1]: CSR offsets of the tour lists
+  uint32_t tour_bp;   // u16 [NB]: BPs in tour order
+  uint32_t hu_mask;   // u64 per tour: HU ranks held
+  uint32_t su_mask;   // 2 x u64 per tour: SU ranks held
+  uint32_t static_words, total_words;
+};
+
+struct DevSol {
+  uint16_t *tour_off, *tour_bp, *bp_off, *bp_field, *hu_tour, *su_tour;
+};
+
+struct SearchState {
+  uint32_t it;
+  uint32_t n_improved;
+  uint64_t cost_best;
+  int64_t t_best;
+  uint32_t use_best;
+  uint32_t trace_rows;
+};
+
+struct TraceRow {
+  uint64_t best_key;
+  uint64_t cost_m;
+  int64_t makespan_s;
+  uint32_t it;
+  uint8_t indicator, use_best, pad[2];
+};
+
+// Everything a kernel needs to know about one instance (passed by value).
+struct InstParams {
+  int32_t NF, NB, NT, NHU, NSU, V;
+  uint32_t flags, cap_hu, cap_su, v_hu;
+  int32_t seg;        // lanes per candidate: power of two >= NT
+  int32_t d_in_lds;   // the distance matrix is staged in LDS too
+  ImageLayout lay;
+  const uint32_t *dist;
+  uint32_t *image;
+  DevSol sol[3];
+  SearchState *st;
+  TraceRow *trace;
+  uint32_t trace_cap;
+  uint64_t *best_key;  // per-instance argmin slot
+  uint16_t *hu_id;     // rank -> HU id
+  uint16_t *su_id;     // rank -> SU id
+};
+
+// Kernel entry points (launch wrappers defined in eval.hip).
+hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t eps_thr,
+                          uint32_t inst_index, hipStream_t s);
+hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, uint32_t inst_index,
+                           uint32_t first, uint32_t n, uint64_t *out, hipStream_t s);
+hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
+                             int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
+                             uint8_t *flags, int grid, hipStream_t s);
+hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
+                              uint32_t inst_index, int grid, hipStream_t s);
+hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t inst_index,
+                         hipStream_t s);
+hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStream_t s);
+size_t eval_lds_bytes(const InstParams &P);
+
+enum { kPrepFromBase = 0, kPrepSearch = 1 };
+enum { kCommitStart = 0, kCommitStep = 1 };
+
+}  // namespace bl
