@@ -243,3 +243,14 @@ def make_replica_instance(seed: int, accept: Optional[Accept] = None) -> Instanc
             init_sus_per_tour=np.full(7, 6, np.int64),
         )
     return _first_accepted(draw, accept)
+
+
+SURROGATE_PARAMS = 16 * 128 + 128 * 128 + 136 * 64 + 64 * 2
+
+
+def surrogate_init_words(seed: int) -> np.ndarray:
+    """Uniform [0, 1) draws for the initial weights of the learned screen
+    (W1 16x128, W2 128x128, W3 136x64, W4 64x2, row-major, in that order);
+    the weights themselves are formed from these draws by each side."""
+    rng = np.random.Generator(np.random.Philox(key=seed + (5 << 96)))
+    return rng.random(SURROGATE_PARAMS)
