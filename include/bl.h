@@ -202,6 +202,95 @@ bl_status bl_search_state_get(bl_ctx *ctx, int32_t inst, bl_search_state *out);
 bl_status bl_search_trace(bl_ctx *ctx, int32_t inst, bl_trace_row *out, uint32_t max_rows,
                           uint32_t *n_rows);
 
+/*
+ * Batches: many independent instances of uneven size searched together, one
+ * persistent evaluation launch per iteration for all of them.  Members are
+ * instances of the same context whose base slot is uploaded; each keeps its
+ * own x*, x_old, state and trace (read with bl_search_state_get /
+ * bl_search_trace on the member id).  Member k draws its candidates with
+ * Philox counter word p->inst_index + k.  n_cand (1 .. 2^24) is the number of
+ * candidates per member per iteration.
+ */
+typedef struct {
+  /* Candidates per work item for members with < 100, 100-199 and >= 200
+   * fields (powers of two, 64 .. 65536). */
+  uint32_t tile[3];
+  /* 0: members in id order; 1: members with more fields first. */
+  uint32_t order_policy;
+} bl_batch_schedule;
+
+bl_status bl_batch_create(bl_ctx *ctx, const int32_t *inst_ids, int32_t n_inst, uint32_t n_cand,
+                          int32_t *batch);
+/* Step 4 for every member (as bl_search_start).  Async. */
+bl_status bl_batch_start(bl_ctx *ctx, int32_t batch, uint32_t trace_capacity);
+/* One iteration of Algorithm 1 for every member; p->n is ignored.  Async. */
+bl_status bl_batch_step(bl_ctx *ctx, int32_t batch, const bl_search_params *p);
+bl_status bl_batch_set_schedule(bl_ctx *ctx, int32_t batch, const bl_batch_schedule *s);
+/* Search the schedule (tile per size class, member order) by timing the
+ * batch's evaluation launch on the current bases, and apply the best one.
+ * With cache_path, a previous result for the same member sizes and n_cand is
+ * read from that JSON file instead, and a new result is added to it.  The
+ * chosen schedule is written to *out (nullable).  Synchronising; the search
+ * state is unchanged. */
+bl_status bl_batch_autotune(bl_ctx *ctx, int32_t batch, const bl_search_params *p,
+                            const char *cache_path, bl_batch_schedule *out);
+
+/*
+ * HIP graphs: n_steps iterations of bl_search_step (one instance) or of
+ * bl_batch_step (a batch) captured once, then replayed with bl_graph_launch
+ * on the context's stream.  The parameters are fixed at capture; capture
+ * after bl_search_start / bl_batch_start (a later start invalidates the
+ * graph).  Iterations keep advancing: each replay continues the search.
+ */
+bl_status bl_search_capture(bl_ctx *ctx, int32_t inst, const bl_search_params *p, uint32_t n_steps,
+                            int32_t *graph);
+bl_status bl_batch_capture(bl_ctx *ctx, int32_t batch, const bl_search_params *p, uint32_t n_steps,
+                           int32_t *graph);
+bl_status bl_graph_launch(bl_ctx *ctx, int32_t graph);
+
+/*
+ * Learned screen (not in the paper): a set encoder over the fields of a
+ * candidate solution.  Per field f (BP b, route predecessor p):
+ *   phi = [x_f, y_f, area, yield, x_b, y_b, D(f,b), D(p,f), 2 n_f D(f,b), D(HQ,f)]
+ *   (scaled by the largest coordinate, area, yield, distance and shuttle
+ *   distance; zero padded to 16) -> 128 -> 128 (ReLU), mean over the fields
+ *   of each BP, mean over the BPs of each tour, concatenated with 8 tour
+ *   features (HU and SU counts, rates and fill times, field and BP counts,
+ *   return leg, 1) -> 64 (ReLU) -> 2 (path share, completion time); path =
+ *   sum over active tours, makespan = max over active tours, both divided by
+ *   the scales c0_m and t0_s.  bf16 MFMA with fp32 accumulation; fp32 master
+ *   weights trained with Adam on (candidate, exact cost) pairs.
+ * Weights are float32 in this order: W1 16x128, b1 128, W2 128x128, b2 128,
+ * W3 136x64, b3 64, W4 64x2, b4 2 (27586 values, row-major).
+ * The instance must have been uploaded with coordinates (xy_m) and at most
+ * 128 BPs.  Candidates are moves against the instance's base slot.
+ */
+#define BL_SUR_PARAMS 27586
+
+typedef struct {
+  float lr, beta1, beta2, adam_eps; /* Adam                                        */
+  uint32_t max_examples;            /* examples per predict / train call           */
+  float c0_m, t0_s;                 /* target scales: path length (m), makespan (s) */
+} bl_sur_config;
+
+bl_status bl_sur_create(bl_ctx *ctx, int32_t inst, const float *weights, const bl_sur_config *cfg,
+                        int32_t *sur);
+bl_status bl_sur_get_weights(bl_ctx *ctx, int32_t sur, float *out);
+bl_status bl_sur_set_weights(bl_ctx *ctx, int32_t sur, const float *weights);
+/* Predictions for n moves: d_out[2 i] = path / c0, d_out[2 i + 1] = makespan / t0.  Async. */
+bl_status bl_sur_predict(bl_ctx *ctx, int32_t sur, const uint64_t *d_moves, uint32_t n, float *d_out);
+/* Sum over the n examples of the gradient of (P - C/c0)^2 + (M - T/t0)^2
+ * into grads (host, BL_SUR_PARAMS floats) and the summed loss into *loss;
+ * examples with an infinite cost or makespan are skipped.  Synchronising. */
+bl_status bl_sur_gradients(bl_ctx *ctx, int32_t sur, const uint64_t *d_moves, const float *d_cost_km,
+                           const int32_t *d_makespan_s, uint32_t n, float *grads, double *loss);
+/* One Adam step on the mean loss of n <= max_examples examples (costs and
+ * makespans as bl_evaluate_batch writes them).  d_loss (nullable, 2 floats):
+ * loss sum and number of examples used.  Async. */
+bl_status bl_sur_train_step(bl_ctx *ctx, int32_t sur, const uint64_t *d_moves,
+                            const float *d_cost_km, const int32_t *d_makespan_s, uint32_t n,
+                            float *d_loss);
+
 /* Kernel timing.  While enabled, every launch of the evaluation kernel made
  * by bl_search_step or bl_evaluate_batch is bracketed by two HIP events on
  * the context's stream.  bl_timing_read synchronises, returns the summed

@@ -54,6 +54,15 @@ class _SearchState(C.Structure):
                 ("t_best_s", C.c_int64)]
 
 
+class _SurConfig(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
+                ("max_examples", C.c_uint32), ("c0_m", C.c_float), ("t0_s", C.c_float)]
+
+
+class _Schedule(C.Structure):
+    _fields_ = [("tile", C.c_uint32 * 3), ("order_policy", C.c_uint32)]
+
+
 class _TraceRow(C.Structure):
     _fields_ = [("best_key", C.c_uint64), ("cost_m", C.c_uint64), ("makespan_s", C.c_int64),
                 ("it", C.c_uint32), ("indicator", C.c_uint8), ("use_best", C.c_uint8),
@@ -80,6 +89,27 @@ _SIGS = {
     "bl_search_state_get": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchState)]),
     "bl_search_trace": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_TraceRow), C.c_uint32,
                                     C.POINTER(C.c_uint32)]),
+    "bl_batch_create": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_uint32,
+                                    C.POINTER(C.c_int32)]),
+    "bl_batch_start": (C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32]),
+    "bl_batch_step": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams)]),
+    "bl_batch_set_schedule": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_Schedule)]),
+    "bl_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams), C.c_char_p,
+                                      C.POINTER(_Schedule)]),
+    "bl_search_capture": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams), C.c_uint32,
+                                      C.POINTER(C.c_int32)]),
+    "bl_batch_capture": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams), C.c_uint32,
+                                     C.POINTER(C.c_int32)]),
+    "bl_graph_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "bl_sur_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.POINTER(_SurConfig),
+                                  C.POINTER(C.c_int32)]),
+    "bl_sur_get_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]),
+    "bl_sur_set_weights": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_float)]),
+    "bl_sur_predict": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint32, C.c_void_p]),
+    "bl_sur_gradients": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
+    "bl_sur_train_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_uint32, C.c_void_p]),
     "bl_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "bl_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint32)]),
 }
@@ -273,3 +303,106 @@ class Context:
         ms, n = C.c_double(), C.c_uint32()
         self._check(self._lib.bl_timing_read(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    # ---------------------------------------------------------- batches --
+    def batch_create(self, inst_ids, n_cand: int) -> int:
+        ids = (C.c_int32 * len(inst_ids))(*inst_ids)
+        out = C.c_int32()
+        self._check(self._lib.bl_batch_create(self._h, ids, len(inst_ids), n_cand, C.byref(out)))
+        return out.value
+
+    def batch_start(self, batch: int, trace_capacity: int = 0):
+        self._check(self._lib.bl_batch_start(self._h, batch, trace_capacity))
+
+    def batch_step(self, batch: int, seed: int, eps_threshold: int, inst_index: int = 0):
+        p = _SearchParams(seed, eps_threshold, 0, inst_index)
+        self._check(self._lib.bl_batch_step(self._h, batch, C.byref(p)))
+
+    def batch_set_schedule(self, batch: int, tiles, order_policy: int):
+        s = _Schedule((C.c_uint32 * 3)(*tiles), order_policy)
+        self._check(self._lib.bl_batch_set_schedule(self._h, batch, C.byref(s)))
+
+    def batch_autotune(self, batch: int, seed: int, eps_threshold: int, cache_path=None,
+                       inst_index: int = 0) -> dict:
+        p = _SearchParams(seed, eps_threshold, 0, inst_index)
+        s = _Schedule()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self._lib.bl_batch_autotune(self._h, batch, C.byref(p), path, C.byref(s)))
+        return dict(tile=list(s.tile), order_policy=s.order_policy)
+
+    # ----------------------------------------------------------- graphs --
+    def search_capture(self, inst_id: int, seed: int, eps_threshold: int, n: int, n_steps: int,
+                       inst_index: int = 0) -> int:
+        p = _SearchParams(seed, eps_threshold, n, inst_index)
+        g = C.c_int32()
+        self._check(self._lib.bl_search_capture(self._h, inst_id, C.byref(p), n_steps, C.byref(g)))
+        return g.value
+
+    def batch_capture(self, batch: int, seed: int, eps_threshold: int, n_steps: int,
+                      inst_index: int = 0) -> int:
+        p = _SearchParams(seed, eps_threshold, 0, inst_index)
+        g = C.c_int32()
+        self._check(self._lib.bl_batch_capture(self._h, batch, C.byref(p), n_steps, C.byref(g)))
+        return g.value
+
+    def graph_launch(self, graph: int):
+        self._check(self._lib.bl_graph_launch(self._h, graph))
+
+    # ---------------------------------------------------- learned screen --
+    def sur_create(self, inst_id: int, weights, c0_m: float, t0_s: float, max_examples: int = 4096,
+                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                   adam_eps: float = 1e-8) -> int:
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        assert w.size == SUR_PARAMS
+        cfg = _SurConfig(lr, beta1, beta2, adam_eps, max_examples, c0_m, t0_s)
+        out = C.c_int32()
+        self._check(self._lib.bl_sur_create(self._h, inst_id, w.ctypes.data_as(C.POINTER(C.c_float)),
+                                            C.byref(cfg), C.byref(out)))
+        return out.value
+
+    def sur_get_weights(self, sur: int) -> np.ndarray:
+        w = np.empty(SUR_PARAMS, dtype=np.float32)
+        self._check(self._lib.bl_sur_get_weights(self._h, sur, w.ctypes.data_as(C.POINTER(C.c_float))))
+        return w
+
+    def sur_set_weights(self, sur: int, weights):
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        self._check(self._lib.bl_sur_set_weights(self._h, sur, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def sur_predict(self, sur: int, d_moves, n: int, d_out):
+        self._check(self._lib.bl_sur_predict(self._h, sur, C.c_void_p(_ptr(d_moves)), n,
+                                             C.c_void_p(_ptr(d_out))))
+
+    def sur_gradients(self, sur: int, d_moves, d_cost, d_mk, n: int):
+        g = np.empty(SUR_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self._lib.bl_sur_gradients(
+            self._h, sur, C.c_void_p(_ptr(d_moves)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_mk)), n,
+            g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+        return g, loss.value
+
+    def sur_train_step(self, sur: int, d_moves, d_cost, d_mk, n: int, d_loss=None):
+        self._check(self._lib.bl_sur_train_step(
+            self._h, sur, C.c_void_p(_ptr(d_moves)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_mk)), n,
+            C.c_void_p(_ptr(d_loss))))
+
+
+SUR_PARAMS = 27586
+SUR_SHAPES = [("W1", (16, 128)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+              ("W3", (136, 64)), ("b3", (64,)), ("W4", (64, 2)), ("b4", (2,))]
+
+
+def sur_glorot_weights(draws) -> np.ndarray:
+    """Initial weights in the library's order from uniform [0, 1) draws
+    (W1, W2, W3, W4 draws in that order): Glorot-uniform weights, zero
+    biases."""
+    out, k = [], 0
+    for name, shape in SUR_SHAPES:
+        n = int(np.prod(shape))
+        if name.startswith("W"):
+            lim = np.sqrt(6.0 / (shape[0] + shape[1]))
+            out.append((np.asarray(draws[k:k + n], dtype=np.float64) * 2 - 1) * lim)
+            k += n
+        else:
+            out.append(np.zeros(n))
+    return np.concatenate([o.reshape(-1) for o in out]).astype(np.float32)

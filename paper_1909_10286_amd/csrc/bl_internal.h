@@ -39,8 +39,9 @@ struct ImageLayout {
   uint32_t pos;       // u16 per field: its position
   uint32_t fbp;       // u16 per field: its BP
   uint32_t fidx;      // u16 per field: its index in the BP's list
-  uint32_t leg_in;    // u32 per position q: D[field(q-1)][field(q)], q=0: D[HQ][field(0)]
-  uint32_t dfb;       // u32 per position: D[field][its BP]
+  uint32_t prec;      // uint4 per position q: {D[field(q-1)][field(q)] (q=0: from HQ),
+                      //   D[field][its BP], area, supply}
+  uint32_t w_q;       // u32 per position: shuttle distance 2 * drives * D[field][its BP]
   uint32_t bp_start;  // u16 per BP: position of its first field
   uint32_t bp_len;    // u16 per BP: number of fields
   uint32_t bp_tour;   // u16 per BP: its tour
@@ -91,6 +92,54 @@ struct InstParams {
   uint16_t *su_id;     // rank -> SU id
 };
 
+// A batch of instances evaluated by one persistent launch.
+struct BatchParams {
+  const InstParams *inst;    // [K] device copies of the members' parameters
+  uint32_t K;
+  uint32_t n;                // candidates per member per iteration
+  uint64_t seed;
+  uint64_t eps_thr;
+  uint32_t index_base;       // member k uses Philox counter word index_base + k
+  uint32_t total_items;
+  const uint32_t *item_off;  // [K+1] first item of each schedule position
+  const uint32_t *order;     // [K] schedule position -> member
+  const uint32_t *tile;      // [K] candidates per item, by member
+  uint32_t *queue;           // [1] next item to pop
+};
+
+// ---- learned screen (set encoder) ----
+// Parameters, float32, in this order: W1 16x128, b1, W2 128x128, b2,
+// W3 136x64 (rows 0..127 read the pooled field embedding, 128..135 the tour
+// features), b3, W4 64x2, b4.
+constexpr int kSurIn = 16, kSurK1 = 32, kSurH = 128, kSurU = 8, kSurA = 64;
+constexpr int kSurOffW1 = 0, kSurOffB1 = 2048, kSurOffW2 = 2176, kSurOffB2 = 18560;
+constexpr int kSurOffW3 = 18688, kSurOffB3 = 27392, kSurOffW4 = 27456, kSurOffB4 = 27584;
+constexpr int kSurParams = 27586;
+
+struct SurDev {
+  float *W, *G, *Mo, *Ve;            // parameters, gradient sums, Adam moments
+  uint16_t *w1t;                      // bf16 [128][32]: w1t[n][k] = W1[k][n] (k >= 16: 0)
+  uint16_t *w2t;                      // bf16 [128][128]: w2t[n][k] = W2[k][n]
+  uint16_t *w2n;                      // bf16 [128][128]: W2 as stored
+  uint16_t *w3et;                     // bf16 [64][128]: w3et[n][k] = W3[k][n], k < 128
+  uint16_t *w3en;                     // bf16 [128][64]: W3 rows 0..127 as stored
+  const float *fstat;                 // [NF][8]: x, y, area, yield, D(HQ,f), 2 n_f / Ws
+  const float *bxy;                   // [NB][2] scaled BP coordinates
+  float inv_ds, inv_c0, inv_t0, inv_rates, inv_fills;
+  uint32_t cap_ex;                    // examples per call (row buffers hold cap_ex * NF rows)
+  uint16_t *phi;                      // [rows][32] bf16 features
+  uint16_t *row_bp;                   // [rows] BP of the row's field in its candidate
+  uint16_t *h1, *h2;                  // [rows][128] bf16 activations
+  float *P;                           // [rows][64] h2 W3[0:128]
+  float *dP;                          // [rows][64] loss gradient w.r.t. P
+  float *ex_u;                        // [ex][NT][8]
+  uint16_t *ex_cnt;                   // [ex][NB] fields per BP in the candidate
+  uint16_t *ex_nb;                    // [ex][NT] BPs per tour
+  uint16_t *ex_btour;                 // [ex][NB] tour of each BP in the candidate
+  float *ex_pred;                     // [ex][2] predicted (path, makespan), scaled
+  float *loss;                        // [2] loss sum, examples counted
+};
+
 // Kernel entry points (launch wrappers defined in eval.hip).
 hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t eps_thr,
                           uint32_t inst_index, hipStream_t s);
@@ -105,6 +154,30 @@ hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t 
                          hipStream_t s);
 hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStream_t s);
 size_t eval_lds_bytes(const InstParams &P);
+int eval_occupancy(const InstParams &P, bool search);
+size_t batch_lds_bytes(uint32_t max_image_words);
+int batch_occupancy(size_t lds);
+hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s);
+hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s);
+hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s);
+hipError_t launch_batch_commit(const BatchParams &B, size_t lds, hipStream_t s);
+
+size_t sur_w1t_elems();
+size_t sur_w2_elems();
+size_t sur_w3et_elems();
+size_t sur_w3en_elems();
+size_t sur_head_lds(const InstParams &P);
+hipError_t sur_setup_attributes();
+hipError_t launch_sur_pack(const SurDev &S, hipStream_t s);
+hipError_t launch_sur_zero(float *p, uint32_t n, hipStream_t s);
+hipError_t launch_sur_forward(const InstParams &P, const SurDev &S, const uint64_t *moves,
+                              uint32_t n, int noop, bool keep_act, int n_cu, hipStream_t s);
+hipError_t launch_sur_head(const InstParams &P, const SurDev &S, uint32_t n, int train,
+                           const float *cost_km, const int32_t *mk, int n_cu, hipStream_t s);
+hipError_t launch_sur_backward(const InstParams &P, const SurDev &S, uint32_t n, int n_cu,
+                               hipStream_t s);
+hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float eps, float scale,
+                           uint32_t step, hipStream_t s);
 
 enum { kPrepFromBase = 0, kPrepSearch = 1 };
 enum { kCommitStart = 0, kCommitStep = 1 };

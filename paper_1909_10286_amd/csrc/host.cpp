@@ -28,6 +28,7 @@ struct Instance {
   // host copies
   int NF = 0, NB = 0, NT = 0, NHU = 0, NSU = 0, V = 0;
   std::vector<uint32_t> dist, area, yld, demand, hu_rate, su_cap, su_speed, su_fill;
+  std::vector<int32_t> xy;  // 2 * V coordinates, empty when not given
   std::vector<uint16_t> init_hu, init_su;
   std::vector<uint64_t> supply;
   uint32_t v_hu = 0, flags = 0;
@@ -42,6 +43,28 @@ struct Instance {
   int occ_batch = 1, occ_search = 1;
 };
 
+// Learned screen of one instance.
+struct Sur {
+  int32_t inst = -1;
+  bl_sur_config cfg{};
+  SurDev D{};
+  std::vector<void *> allocs;
+  uint32_t step = 0;
+};
+
+struct Batch {
+  std::vector<int32_t> members;
+  uint32_t n = 0;
+  bl_batch_schedule sched{{1024, 1024, 1024}, 1};
+  InstParams *d_inst = nullptr;  // [K]
+  uint32_t *d_sched = nullptr;   // item_off[K+1] | order[K] | tile[K] | queue[1]
+  uint32_t total_items = 0;
+  uint32_t max_image_words = 0;
+  size_t lds = 0;
+  int occ = 1;
+  bool started = false;
+};
+
 }  // namespace
 
 struct bl_ctx {
@@ -50,6 +73,11 @@ struct bl_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::vector<std::unique_ptr<Instance>> inst;
+  std::vector<std::unique_ptr<Batch>> batches;
+  std::vector<std::unique_ptr<Sur>> surs;
+  std::vector<hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;  // private stream used only while capturing
+  bool capturing = false;
   // kernel timing: event pairs recorded around evaluation launches
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -102,6 +130,10 @@ struct Alloc {
   uint32_t u64(uint32_t n) {
     words = (words + 1) & ~1u;
     return u32(2 * n);
+  }
+  uint32_t u128(uint32_t n) {
+    words = (words + 3) & ~3u;
+    return u32(4 * n);
   }
 };
 
@@ -163,7 +195,7 @@ bl_status validate_solution(bl_ctx *c, const Instance &I, const bl_solution *s) 
 
 // Records one timing event (when enabled); returns false on a HIP error.
 hipError_t timing_mark(bl_ctx *c) {
-  if (!c->timing) return hipSuccess;
+  if (!c->timing || c->capturing) return hipSuccess;
   if (c->events_used == c->events.size()) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
@@ -173,11 +205,204 @@ hipError_t timing_mark(bl_ctx *c) {
   return hipEventRecord(c->events[c->events_used++], c->stream);
 }
 
+hipStream_t work_stream(const bl_ctx *c) { return c->capturing ? c->capture_stream : c->stream; }
+
+bl_status alloc_trace(bl_ctx *c, Instance *I, uint32_t cap) {
+  if (cap == I->P.trace_cap) return BL_OK;
+  (void)hipFree(I->d_trace);
+  I->d_trace = nullptr;
+  I->P.trace_cap = 0;
+  I->P.trace = nullptr;
+  if (cap) {
+    HIP_TRY(c, hipMalloc(&I->d_trace, (size_t)cap * sizeof(TraceRow)));
+    I->P.trace = I->d_trace;
+    I->P.trace_cap = cap;
+  }
+  return BL_OK;
+}
+
 int grid_for(const bl_ctx *c, const Instance &I, uint32_t n, bool search) {
   const uint32_t per_block = 4u * (64u / (uint32_t)I.P.seg);
   const uint32_t need = (n + per_block - 1) / per_block;
   const uint32_t cap = (uint32_t)c->n_cu * (uint32_t)(search ? I.occ_search : I.occ_batch);
   return (int)std::max<uint32_t>(1u, std::min(need, cap));
+}
+
+bl_status search_step_on(bl_ctx *c, Instance *I, const bl_search_params *p, hipStream_t q) {
+  HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
+  HIP_TRY(c, timing_mark(c));
+  HIP_TRY(c, launch_eval_search(I->P, p->seed, p->n, p->inst_index, grid_for(c, *I, p->n, true), q));
+  HIP_TRY(c, timing_mark(c));
+  HIP_TRY(c, launch_commit(I->P, kCommitStep, p->seed, p->inst_index, q));
+  return BL_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+Batch *get_batch(bl_ctx *c, int32_t id) {
+  if (!c || id < 0 || id >= (int32_t)c->batches.size()) return nullptr;
+  return c->batches[id].get();
+}
+
+int size_class(int nf) { return nf < 100 ? 0 : (nf < 200 ? 1 : 2); }
+
+bl_status upload_member_params(bl_ctx *c, Batch &B) {
+  std::vector<InstParams> ps;
+  for (int32_t id : B.members) ps.push_back(c->inst[id]->P);
+  HIP_TRY(c, hipMemcpy(B.d_inst, ps.data(), ps.size() * sizeof(InstParams), hipMemcpyHostToDevice));
+  return BL_OK;
+}
+
+bl_status apply_schedule(bl_ctx *c, Batch &B, const bl_batch_schedule &s) {
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t t = s.tile[k];
+    if (t < 64 || t > 65536 || (t & (t - 1)))
+      return fail(c, BL_EINVAL, "tile[%d] = %u must be a power of two in 64..65536", k, t);
+  }
+  if (s.order_policy > 1) return fail(c, BL_EINVAL, "order_policy must be 0 or 1");
+  const uint32_t K = (uint32_t)B.members.size();
+  std::vector<uint32_t> order(K);
+  std::iota(order.begin(), order.end(), 0u);
+  if (s.order_policy == 1)
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      return c->inst[B.members[a]]->NF > c->inst[B.members[b]]->NF;
+    });
+  std::vector<uint32_t> tile(K), off(K + 1, 0);
+  for (uint32_t k = 0; k < K; ++k) tile[k] = s.tile[size_class(c->inst[B.members[k]]->NF)];
+  for (uint32_t p = 0; p < K; ++p) off[p + 1] = off[p] + (B.n + tile[order[p]] - 1) / tile[order[p]];
+  std::vector<uint32_t> buf;
+  buf.insert(buf.end(), off.begin(), off.end());
+  buf.insert(buf.end(), order.begin(), order.end());
+  buf.insert(buf.end(), tile.begin(), tile.end());
+  buf.push_back(0u);
+  HIP_TRY(c, hipMemcpy(B.d_sched, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
+  B.total_items = off[K];
+  B.sched = s;
+  return BL_OK;
+}
+
+BatchParams batch_params(const Batch &B, const bl_search_params *p) {
+  const uint32_t K = (uint32_t)B.members.size();
+  BatchParams bp;
+  bp.inst = B.d_inst;
+  bp.K = K;
+  bp.n = B.n;
+  bp.seed = p ? p->seed : 0;
+  bp.eps_thr = p ? p->eps_threshold : 0;
+  bp.index_base = p ? p->inst_index : 0;
+  bp.total_items = B.total_items;
+  bp.item_off = B.d_sched;
+  bp.order = B.d_sched + K + 1;
+  bp.tile = B.d_sched + 2 * K + 1;
+  bp.queue = B.d_sched + 3 * K + 1;
+  return bp;
+}
+
+int batch_grid(const bl_ctx *c, const Batch &B) {
+  return (int)std::max<uint32_t>(1u, std::min<uint32_t>(B.total_items, (uint32_t)(c->n_cu * B.occ)));
+}
+
+bl_status batch_step_on(bl_ctx *c, Batch &B, const bl_search_params *p, hipStream_t q) {
+  const BatchParams bp = batch_params(B, p);
+  HIP_TRY(c, launch_batch_prepare(bp, q));
+  HIP_TRY(c, timing_mark(c));
+  HIP_TRY(c, launch_batch_eval(bp, batch_grid(c, B), B.lds, q));
+  HIP_TRY(c, timing_mark(c));
+  HIP_TRY(c, launch_batch_commit(bp, B.lds, q));
+  return BL_OK;
+}
+
+// FNV-1a over the member sizes and the candidate count.
+std::string batch_signature(const bl_ctx *c, const Batch &B) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(B.members.size());
+  mix(B.n);
+  for (int32_t id : B.members) {
+    const Instance &I = *c->inst[id];
+    mix(I.NF);
+    mix(I.NB);
+    mix(I.NT);
+    mix(I.NHU);
+    mix(I.NSU);
+  }
+  char buf[32];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+bool read_file(const char *path, std::string &out) {
+  FILE *f = fopen(path, "rb");
+  if (!f) return false;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) out.append(buf, k);
+  fclose(f);
+  return true;
+}
+
+bool cache_lookup(const std::string &text, const std::string &sig, bl_batch_schedule &s) {
+  const size_t at = text.find("\"" + sig + "\"");
+  if (at == std::string::npos) return false;
+  unsigned a, b, d, pol;
+  if (sscanf(text.c_str() + at + sig.size() + 2, " : {\"tile\": [%u, %u, %u], \"order_policy\": %u",
+             &a, &b, &d, &pol) != 4)
+    return false;
+  s.tile[0] = a;
+  s.tile[1] = b;
+  s.tile[2] = d;
+  s.order_policy = pol;
+  return true;
+}
+
+bool cache_store(const char *path, std::string text, const std::string &sig,
+                 const bl_batch_schedule &s, double ms) {
+  char entry[256];
+  snprintf(entry, sizeof entry,
+           "  \"%s\": {\"tile\": [%u, %u, %u], \"order_policy\": %u, \"eval_ms\": %.4f}", sig.c_str(),
+           s.tile[0], s.tile[1], s.tile[2], s.order_policy, ms);
+  const size_t close = text.rfind('}');
+  if (text.find('"') == std::string::npos || close == std::string::npos)
+    text = std::string("{\n") + entry + "\n}\n";
+  else
+    text = text.substr(0, text.find_last_not_of(" \n\t", close - 1) + 1) + ",\n" + entry + "\n}\n";
+  FILE *f = fopen(path, "wb");
+  if (!f) return false;
+  const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+  return fclose(f) == 0 && ok;
+}
+
+// ----------------------------------------------------------------- graphs
+
+template <class Body>
+bl_status capture_steps(bl_ctx *c, uint32_t n_steps, Body body, int32_t *graph) {
+  if (!graph || n_steps == 0) return fail(c, BL_EINVAL, "bad graph arguments");
+  if (!c->capture_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
+  c->capturing = true;
+  bl_status st = BL_OK;
+  for (uint32_t s = 0; s < n_steps && st == BL_OK; ++s) st = body(c->capture_stream);
+  c->capturing = false;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+  if (st != BL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipGraphInstantiate");
+  c->graphs.push_back(ex);
+  *graph = (int32_t)c->graphs.size() - 1;
+  return BL_OK;
 }
 
 }  // namespace
@@ -222,6 +447,12 @@ void bl_destroy(bl_ctx *ctx) {
   (void)hipDeviceSynchronize();
   for (auto &I : ctx->inst) free_instance(I.get());
   for (auto e : ctx->events) (void)hipEventDestroy(e);
+  for (auto g : ctx->graphs) (void)hipGraphExecDestroy(g);
+  for (auto &B : ctx->batches) {
+    (void)hipFree(B->d_inst);
+    (void)hipFree(B->d_sched);
+  }
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
 }
 
@@ -267,6 +498,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   I->su_speed.assign(in->su_speed_mph, in->su_speed_mph + NSU);
   I->su_fill.assign(in->su_fill_s, in->su_fill_s + NSU);
   I->v_hu = in->hu_speed_mph;
+  if (in->xy_m) I->xy.assign(in->xy_m, in->xy_m + 2 * (size_t)V);
   I->flags = in->flags;
   for (int h = 0; h < NHU; ++h)
     if (I->hu_rate[h] == 0) return fail(c, BL_EINVAL, "hu_rate[%d] must be > 0", h);
@@ -291,6 +523,12 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
     shuttle_bound += 2ull * nsh[f] * dmax;
   }
   if (tot_supply >= (1ull << 32)) return fail(c, BL_EINVAL, "total supply >= 2^32 kg");
+  for (int f = 0; f < NF; ++f) {
+    uint32_t dfmax = 0;
+    for (int b = 0; b < NB; ++b) dfmax = std::max(dfmax, I->dist[(size_t)(1 + NB + f) * V + 1 + b]);
+    if (2ull * nsh[f] * dfmax >= (1ull << 32))
+      return fail(c, BL_EINVAL, "shuttle distance of field %d >= 2^32 m", f);
+  }
   if (tot_area >= (1ull << 32)) return fail(c, BL_EINVAL, "total area >= 2^32");
   uint64_t tot_demand = 0;
   for (int b = 0; b < NB; ++b) tot_demand += I->demand[b];
@@ -332,7 +570,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   L.hu_rank = al.u16(NHU); L.su_rank = al.u16(NSU);
   L.static_words = al.words;
   L.seq = al.u16(NF); L.pos = al.u16(NF); L.fbp = al.u16(NF); L.fidx = al.u16(NF);
-  L.leg_in = al.u32(NF); L.dfb = al.u32(NF);
+  L.prec = al.u128(NF); L.w_q = al.u32(NF);
   L.bp_start = al.u16(NB); L.bp_len = al.u16(NB); L.bp_tour = al.u16(NB); L.bp_idx = al.u16(NB);
   L.tour_off = al.u16(NT + 1); L.tour_bp = al.u16(NB);
   L.hu_mask = al.u64(NT); L.su_mask = al.u64(2 * NT);
@@ -387,7 +625,9 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   P.cap_su = in->cap_su ? in->cap_su : (uint32_t)(NSU + NT);
   P.v_hu = in->hu_speed_mph;
   P.seg = (int32_t)next_pow2((uint32_t)NT);
-  size_t dlds_max = 64 * 1024;
+  // Staging the whole matrix pays only while it is small: a large LDS
+  // footprint costs more occupancy than the band-plus-L2 lookups it saves.
+  size_t dlds_max = 16 * 1024;
   if (const char *env = getenv("BL_D_LDS_MAX_BYTES")) dlds_max = (size_t)strtoull(env, nullptr, 10);
   P.d_in_lds = ((size_t)L.total_words + (size_t)V * V) * 4 <= dlds_max ? 1 : 0;
   P.lay = L;
@@ -570,17 +810,8 @@ bl_status bl_search_start(bl_ctx *c, int32_t id, uint32_t trace_capacity) {
   if (!I->base_ready) return fail(c, BL_ESTATE, "no base solution uploaded");
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (trace_capacity != I->P.trace_cap) {
-    (void)hipFree(I->d_trace);
-    I->d_trace = nullptr;
-    I->P.trace_cap = 0;
-    I->P.trace = nullptr;
-    if (trace_capacity) {
-      HIP_TRY(c, hipMalloc(&I->d_trace, (size_t)trace_capacity * sizeof(TraceRow)));
-      I->P.trace = I->d_trace;
-      I->P.trace_cap = trace_capacity;
-    }
-  }
+  bl_status st = alloc_trace(c, I, trace_capacity);
+  if (st != BL_OK) return st;
   HIP_TRY(c, launch_commit(I->P, kCommitStart, 0, 0, c->stream));
   I->started = true;
   return BL_OK;
@@ -594,13 +825,7 @@ bl_status bl_search_step(bl_ctx *c, int32_t id, const bl_search_params *p) {
   if (p->n == 0 || p->n > kMaxCand) return fail(c, BL_EINVAL, "n %u out of 1..2^24", p->n);
   if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
   HIP_TRY(c, hipSetDevice(c->device));
-  hipStream_t q = c->stream;
-  HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
-  HIP_TRY(c, timing_mark(c));
-  HIP_TRY(c, launch_eval_search(I->P, p->seed, p->n, p->inst_index, grid_for(c, *I, p->n, true), q));
-  HIP_TRY(c, timing_mark(c));
-  HIP_TRY(c, launch_commit(I->P, kCommitStep, p->seed, p->inst_index, q));
-  return BL_OK;
+  return search_step_on(c, I, p, work_stream(c));
 }
 
 bl_status bl_search_state_get(bl_ctx *c, int32_t id, bl_search_state *out) {
@@ -635,6 +860,388 @@ bl_status bl_search_trace(bl_ctx *c, int32_t id, bl_trace_row *out, uint32_t max
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   *n_rows = rows;
+  return BL_OK;
+}
+
+bl_status bl_batch_create(bl_ctx *c, const int32_t *ids, int32_t n_inst, uint32_t n_cand,
+                          int32_t *batch) {
+  if (!c) return BL_EINVAL;
+  if (!ids || !batch || n_inst < 1) return fail(c, BL_EINVAL, "bad batch arguments");
+  if (n_cand == 0 || n_cand > kMaxCand) return fail(c, BL_EINVAL, "n_cand %u out of 1..2^24", n_cand);
+  auto B = std::make_unique<Batch>();
+  for (int32_t k = 0; k < n_inst; ++k) {
+    Instance *I = get_inst(c, ids[k]);
+    if (!I) return fail(c, BL_EINVAL, "bad instance id %d", ids[k]);
+    if (!I->base_ready) return fail(c, BL_ESTATE, "member %d has no base solution", ids[k]);
+    for (int32_t j = 0; j < k; ++j)
+      if (ids[j] == ids[k]) return fail(c, BL_EINVAL, "instance %d listed twice", ids[k]);
+    B->members.push_back(ids[k]);
+    B->max_image_words = std::max(B->max_image_words, I->P.lay.total_words);
+  }
+  B->n = n_cand;
+  B->lds = batch_lds_bytes(B->max_image_words);
+  if (B->lds > 160 * 1024) return fail(c, BL_EINVAL, "member image exceeds LDS");
+  HIP_TRY(c, hipSetDevice(c->device));
+  B->occ = batch_occupancy(B->lds);
+  const size_t K = B->members.size();
+  HIP_TRY(c, hipMalloc(&B->d_inst, K * sizeof(InstParams)));
+  if (hipMalloc(&B->d_sched, (3 * K + 2) * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(B->d_inst);
+    return fail(c, BL_ENOMEM, "batch schedule allocation");
+  }
+  Batch *R = B.get();
+  c->batches.push_back(std::move(B));
+  bl_status st = upload_member_params(c, *R);
+  if (st == BL_OK) st = apply_schedule(c, *R, R->sched);
+  if (st != BL_OK) return st;
+  *batch = (int32_t)c->batches.size() - 1;
+  return BL_OK;
+}
+
+bl_status bl_batch_start(bl_ctx *c, int32_t id, uint32_t trace_capacity) {
+  Batch *B = get_batch(c, id);
+  if (!B) return fail(c, BL_EINVAL, "bad batch id %d", id);
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int32_t m : B->members) {
+    bl_status st = alloc_trace(c, c->inst[m].get(), trace_capacity);
+    if (st != BL_OK) return st;
+  }
+  bl_status st = upload_member_params(c, *B);
+  if (st != BL_OK) return st;
+  HIP_TRY(c, launch_batch_start(batch_params(*B, nullptr), B->lds, c->stream));
+  for (int32_t m : B->members) c->inst[m]->started = true;
+  B->started = true;
+  return BL_OK;
+}
+
+bl_status bl_batch_step(bl_ctx *c, int32_t id, const bl_search_params *p) {
+  Batch *B = get_batch(c, id);
+  if (!B) return fail(c, BL_EINVAL, "bad batch id %d", id);
+  if (!p) return fail(c, BL_EINVAL, "null params");
+  if (!B->started) return fail(c, BL_ESTATE, "bl_batch_start not called");
+  if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return batch_step_on(c, *B, p, work_stream(c));
+}
+
+bl_status bl_batch_set_schedule(bl_ctx *c, int32_t id, const bl_batch_schedule *s) {
+  Batch *B = get_batch(c, id);
+  if (!B) return fail(c, BL_EINVAL, "bad batch id %d", id);
+  if (!s) return fail(c, BL_EINVAL, "null schedule");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return apply_schedule(c, *B, *s);
+}
+
+bl_status bl_batch_autotune(bl_ctx *c, int32_t id, const bl_search_params *p, const char *cache_path,
+                            bl_batch_schedule *out) {
+  Batch *B = get_batch(c, id);
+  if (!B) return fail(c, BL_EINVAL, "bad batch id %d", id);
+  if (!p) return fail(c, BL_EINVAL, "null params");
+  if (!B->started) return fail(c, BL_ESTATE, "bl_batch_start not called");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const std::string sig = batch_signature(c, *B);
+  std::string text;
+  const bool have_file = cache_path && read_file(cache_path, text);
+  bl_batch_schedule best{};
+  if (have_file && cache_lookup(text, sig, best)) {
+    bl_status st = apply_schedule(c, *B, best);
+    if (st != BL_OK) return st;
+    if (out) *out = best;
+    return BL_OK;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  // Median of three timed evaluation launches (the bases stay as they are;
+  // only the per-member argmin slots are touched, and the next prepare resets
+  // them).
+  auto time_sched = [&](const bl_batch_schedule &s, double &ms) -> bl_status {
+    bl_status st = apply_schedule(c, *B, s);
+    if (st != BL_OK) return st;
+    const BatchParams bp = batch_params(*B, p);
+    double t[3];
+    for (int r = 0; r < 3; ++r) {
+      HIP_TRY(c, hipEventRecord(e0, c->stream));
+      HIP_TRY(c, launch_batch_eval(bp, batch_grid(c, *B), B->lds, c->stream));
+      HIP_TRY(c, hipEventRecord(e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      float f = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+      t[r] = f;
+    }
+    std::sort(t, t + 3);
+    ms = t[1];
+    return BL_OK;
+  };
+  bool present[3] = {false, false, false};
+  for (int32_t m : B->members) present[size_class(c->inst[m]->NF)] = true;
+  const uint32_t tiles[] = {256, 512, 1024, 2048, 4096};
+  best = bl_batch_schedule{{1024, 1024, 1024}, 1};
+  double best_ms = 0;
+  bl_status st = time_sched(best, best_ms);
+  // Coordinate descent: one size class at a time, then the member order.
+  for (int k = 0; k < 3 && st == BL_OK; ++k) {
+    if (!present[k]) continue;
+    for (uint32_t t : tiles) {
+      bl_batch_schedule s = best;
+      s.tile[k] = t;
+      double ms = 0;
+      if ((st = time_sched(s, ms)) != BL_OK) break;
+      if (ms < best_ms) best_ms = ms, best = s;
+    }
+  }
+  if (st == BL_OK) {
+    bl_batch_schedule s = best;
+    s.order_policy = 1 - s.order_policy;
+    double ms = 0;
+    st = time_sched(s, ms);
+    if (st == BL_OK && ms < best_ms) best_ms = ms, best = s;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != BL_OK) return st;
+  st = apply_schedule(c, *B, best);
+  if (st != BL_OK) return st;
+  if (cache_path && !cache_store(cache_path, have_file ? text : std::string(), sig, best, best_ms))
+    return fail(c, BL_EINVAL, "cannot write cache %s", cache_path);
+  if (out) *out = best;
+  return BL_OK;
+}
+
+bl_status bl_search_capture(bl_ctx *c, int32_t id, const bl_search_params *p, uint32_t n_steps,
+                            int32_t *graph) {
+  Instance *I = get_inst(c, id);
+  if (!I) return fail(c, BL_EINVAL, "bad instance id %d", id);
+  if (!p) return fail(c, BL_EINVAL, "null params");
+  if (!I->started) return fail(c, BL_ESTATE, "bl_search_start not called");
+  if (p->n == 0 || p->n > kMaxCand) return fail(c, BL_EINVAL, "n %u out of 1..2^24", p->n);
+  if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return capture_steps(c, n_steps, [&](hipStream_t q) { return search_step_on(c, I, p, q); }, graph);
+}
+
+bl_status bl_batch_capture(bl_ctx *c, int32_t id, const bl_search_params *p, uint32_t n_steps,
+                           int32_t *graph) {
+  Batch *B = get_batch(c, id);
+  if (!B) return fail(c, BL_EINVAL, "bad batch id %d", id);
+  if (!p) return fail(c, BL_EINVAL, "null params");
+  if (!B->started) return fail(c, BL_ESTATE, "bl_batch_start not called");
+  if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return capture_steps(c, n_steps, [&](hipStream_t q) { return batch_step_on(c, *B, p, q); }, graph);
+}
+
+bl_status bl_graph_launch(bl_ctx *c, int32_t graph) {
+  if (!c) return BL_EINVAL;
+  if (graph < 0 || graph >= (int32_t)c->graphs.size()) return fail(c, BL_EINVAL, "bad graph id %d", graph);
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipGraphLaunch(c->graphs[graph], c->stream));
+  return BL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- learned screen
+
+namespace {
+
+Sur *get_sur(bl_ctx *c, int32_t id) {
+  if (!c || id < 0 || id >= (int32_t)c->surs.size()) return nullptr;
+  return c->surs[id].get();
+}
+
+template <class T>
+bl_status sur_alloc(bl_ctx *c, Sur &S, T *&p, size_t n) {
+  void *q = nullptr;
+  HIP_TRY(c, hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+  S.allocs.push_back(q);
+  p = (T *)q;
+  return BL_OK;
+}
+
+bl_status sur_grads_on(bl_ctx *c, Sur &S, Instance &I, const uint64_t *d_moves, const float *cost,
+                       const int32_t *mk, uint32_t n) {
+  HIP_TRY(c, launch_sur_zero(S.D.loss, 2, c->stream));
+  HIP_TRY(c, launch_sur_forward(I.P, S.D, d_moves, n, 0, true, c->n_cu, c->stream));
+  HIP_TRY(c, launch_sur_head(I.P, S.D, n, 1, cost, mk, c->n_cu, c->stream));
+  HIP_TRY(c, launch_sur_backward(I.P, S.D, n, c->n_cu, c->stream));
+  return BL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bl_status bl_sur_create(bl_ctx *c, int32_t inst, const float *weights, const bl_sur_config *cfg,
+                        int32_t *sur) {
+  Instance *I = get_inst(c, inst);
+  if (!I) return fail(c, BL_EINVAL, "bad instance id %d", inst);
+  if (!weights || !cfg || !sur) return fail(c, BL_EINVAL, "null argument");
+  if (I->xy.empty()) return fail(c, BL_EINVAL, "the instance was uploaded without coordinates");
+  if (I->NB > 128) return fail(c, BL_EINVAL, "the learned screen supports at most 128 BPs");
+  if (cfg->max_examples == 0 || !(cfg->c0_m > 0.f) || !(cfg->t0_s > 0.f) || !(cfg->lr > 0.f))
+    return fail(c, BL_EINVAL, "bad surrogate configuration");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, sur_setup_attributes());
+  auto S = std::make_unique<Sur>();
+  S->inst = inst;
+  S->cfg = *cfg;
+  SurDev &D = S->D;
+  const int NF = I->NF, NB = I->NB, NT = I->NT, V = I->V;
+  // Scales: largest |coordinate|, area, yield, distance, shuttle distance.
+  double ls = 1, as = 1, ys = 1, ds = 1, ws = 1;
+  for (int32_t v : I->xy) ls = std::max(ls, (double)std::abs(v));
+  for (int f = 0; f < NF; ++f) {
+    as = std::max(as, (double)I->area[f]);
+    ys = std::max(ys, (double)I->yld[f]);
+  }
+  for (uint32_t d : I->dist) ds = std::max(ds, (double)d);
+  uint64_t capsum = 0;
+  for (uint32_t cap : I->su_cap) capsum += cap;
+  const uint64_t cbar = capsum / (uint64_t)I->NSU;
+  std::vector<double> nsh(NF);
+  for (int f = 0; f < NF; ++f) {
+    nsh[f] = (double)((I->supply[f] + cbar - 1) / cbar);
+    uint32_t dm = 0;
+    for (int b = 0; b < NB; ++b) dm = std::max(dm, I->dist[(size_t)(1 + NB + f) * V + 1 + b]);
+    ws = std::max(ws, 2.0 * nsh[f] * dm);
+  }
+  std::vector<float> fstat((size_t)NF * 8, 0.f), bxy((size_t)NB * 2);
+  for (int f = 0; f < NF; ++f) {
+    const int v = 1 + NB + f;
+    fstat[f * 8 + 0] = (float)(I->xy[2 * v] / ls);
+    fstat[f * 8 + 1] = (float)(I->xy[2 * v + 1] / ls);
+    fstat[f * 8 + 2] = (float)(I->area[f] / as);
+    fstat[f * 8 + 3] = (float)(I->yld[f] / ys);
+    fstat[f * 8 + 4] = (float)(I->dist[v] / ds);
+    fstat[f * 8 + 5] = (float)(2.0 * nsh[f] / ws);
+  }
+  for (int b = 0; b < NB; ++b) {
+    bxy[2 * b] = (float)(I->xy[2 * (1 + b)] / ls);
+    bxy[2 * b + 1] = (float)(I->xy[2 * (1 + b) + 1] / ls);
+  }
+  double rates = 0, fills = 0;
+  for (uint32_t r : I->hu_rate) rates += r;
+  for (uint32_t f : I->su_fill) fills += f;
+  D.inv_ds = (float)(1.0 / ds);
+  D.inv_c0 = 1.f / cfg->c0_m;
+  D.inv_t0 = 1.f / cfg->t0_s;
+  D.inv_rates = (float)(1.0 / rates);
+  D.inv_fills = (float)(fills > 0 ? 1.0 / fills : 0.0);
+  D.cap_ex = cfg->max_examples;
+  const size_t rows = (size_t)cfg->max_examples * NF;
+  Sur &R = *S;
+  bl_status st = BL_OK;
+  float *fs_d = nullptr, *bxy_d = nullptr;
+  if ((st = sur_alloc(c, R, D.W, kSurParams)) || (st = sur_alloc(c, R, D.G, kSurParams)) ||
+      (st = sur_alloc(c, R, D.Mo, kSurParams)) || (st = sur_alloc(c, R, D.Ve, kSurParams)) ||
+      (st = sur_alloc(c, R, D.w1t, sur_w1t_elems())) || (st = sur_alloc(c, R, D.w2t, sur_w2_elems())) ||
+      (st = sur_alloc(c, R, D.w2n, sur_w2_elems())) || (st = sur_alloc(c, R, D.w3et, sur_w3et_elems())) ||
+      (st = sur_alloc(c, R, D.w3en, sur_w3en_elems())) || (st = sur_alloc(c, R, fs_d, fstat.size())) ||
+      (st = sur_alloc(c, R, bxy_d, bxy.size())) || (st = sur_alloc(c, R, D.phi, rows * kSurK1)) ||
+      (st = sur_alloc(c, R, D.row_bp, rows)) || (st = sur_alloc(c, R, D.h1, rows * kSurH)) ||
+      (st = sur_alloc(c, R, D.h2, rows * kSurH)) || (st = sur_alloc(c, R, D.P, rows * kSurA)) ||
+      (st = sur_alloc(c, R, D.dP, rows * kSurA)) ||
+      (st = sur_alloc(c, R, D.ex_u, (size_t)cfg->max_examples * NT * kSurU)) ||
+      (st = sur_alloc(c, R, D.ex_cnt, (size_t)cfg->max_examples * NB)) ||
+      (st = sur_alloc(c, R, D.ex_nb, (size_t)cfg->max_examples * NT)) ||
+      (st = sur_alloc(c, R, D.ex_btour, (size_t)cfg->max_examples * NB)) ||
+      (st = sur_alloc(c, R, D.ex_pred, (size_t)cfg->max_examples * 2)) ||
+      (st = sur_alloc(c, R, D.loss, 2))) {
+    for (void *p : R.allocs) (void)hipFree(p);
+    return st;
+  }
+  D.fstat = fs_d;
+  D.bxy = bxy_d;
+  HIP_TRY(c, hipMemcpy(fs_d, fstat.data(), fstat.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(bxy_d, bxy.data(), bxy.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(D.W, weights, kSurParams * 4, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemset(D.G, 0, kSurParams * 4));
+  HIP_TRY(c, hipMemset(D.Mo, 0, kSurParams * 4));
+  HIP_TRY(c, hipMemset(D.Ve, 0, kSurParams * 4));
+  HIP_TRY(c, launch_sur_pack(D, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->surs.push_back(std::move(S));
+  *sur = (int32_t)c->surs.size() - 1;
+  return BL_OK;
+}
+
+bl_status bl_sur_get_weights(bl_ctx *c, int32_t id, float *out) {
+  Sur *S = get_sur(c, id);
+  if (!S || !out) return fail(c, BL_EINVAL, "bad surrogate or null output");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(out, S->D.W, kSurParams * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return BL_OK;
+}
+
+bl_status bl_sur_set_weights(bl_ctx *c, int32_t id, const float *w) {
+  Sur *S = get_sur(c, id);
+  if (!S || !w) return fail(c, BL_EINVAL, "bad surrogate or null weights");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(S->D.W, w, kSurParams * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_sur_pack(S->D, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return BL_OK;
+}
+
+bl_status bl_sur_predict(bl_ctx *c, int32_t id, const uint64_t *d_moves, uint32_t n, float *d_out) {
+  Sur *S = get_sur(c, id);
+  if (!S) return fail(c, BL_EINVAL, "bad surrogate id %d", id);
+  Instance *I = c->inst[S->inst].get();
+  if (!I->base_ready) return fail(c, BL_ESTATE, "no base solution uploaded");
+  if (n && (!d_moves || !d_out)) return fail(c, BL_EINVAL, "null buffer");
+  HIP_TRY(c, hipSetDevice(c->device));
+  for (uint32_t done = 0; done < n; done += S->D.cap_ex) {
+    const uint32_t k = std::min(n - done, S->D.cap_ex);
+    HIP_TRY(c, launch_sur_forward(I->P, S->D, d_moves + done, k, 0, false, c->n_cu, c->stream));
+    HIP_TRY(c, launch_sur_head(I->P, S->D, k, 0, nullptr, nullptr, c->n_cu, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_out + 2 * (size_t)done, S->D.ex_pred, (size_t)k * 8,
+                              hipMemcpyDeviceToDevice, c->stream));
+  }
+  return BL_OK;
+}
+
+bl_status bl_sur_gradients(bl_ctx *c, int32_t id, const uint64_t *d_moves, const float *d_cost_km,
+                           const int32_t *d_makespan_s, uint32_t n, float *grads, double *loss) {
+  Sur *S = get_sur(c, id);
+  if (!S) return fail(c, BL_EINVAL, "bad surrogate id %d", id);
+  Instance *I = c->inst[S->inst].get();
+  if (!I->base_ready) return fail(c, BL_ESTATE, "no base solution uploaded");
+  if (n == 0 || n > S->D.cap_ex) return fail(c, BL_EINVAL, "n %u out of 1..max_examples", n);
+  if (!d_moves || !d_cost_km || !d_makespan_s || !grads || !loss) return fail(c, BL_EINVAL, "null buffer");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, launch_sur_zero(S->D.G, kSurParams, c->stream));
+  bl_status st = sur_grads_on(c, *S, *I, d_moves, d_cost_km, d_makespan_s, n);
+  if (st != BL_OK) return st;
+  float l[2];
+  HIP_TRY(c, hipMemcpyAsync(grads, S->D.G, kSurParams * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(l, S->D.loss, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, launch_sur_zero(S->D.G, kSurParams, c->stream));
+  *loss = l[0];
+  return BL_OK;
+}
+
+bl_status bl_sur_train_step(bl_ctx *c, int32_t id, const uint64_t *d_moves, const float *d_cost_km,
+                            const int32_t *d_makespan_s, uint32_t n, float *d_loss) {
+  Sur *S = get_sur(c, id);
+  if (!S) return fail(c, BL_EINVAL, "bad surrogate id %d", id);
+  Instance *I = c->inst[S->inst].get();
+  if (!I->base_ready) return fail(c, BL_ESTATE, "no base solution uploaded");
+  if (n == 0 || n > S->D.cap_ex) return fail(c, BL_EINVAL, "n %u out of 1..max_examples", n);
+  if (!d_moves || !d_cost_km || !d_makespan_s) return fail(c, BL_EINVAL, "null buffer");
+  HIP_TRY(c, hipSetDevice(c->device));
+  bl_status st = sur_grads_on(c, *S, *I, d_moves, d_cost_km, d_makespan_s, n);
+  if (st != BL_OK) return st;
+  S->step += 1;
+  const bl_sur_config &g = S->cfg;
+  HIP_TRY(c, launch_sur_adam(S->D, g.lr, g.beta1, g.beta2, g.adam_eps, 1.f / (float)n, S->step, c->stream));
+  HIP_TRY(c, launch_sur_pack(S->D, c->stream));
+  if (d_loss) HIP_TRY(c, hipMemcpyAsync(d_loss, S->D.loss, 8, hipMemcpyDeviceToDevice, c->stream));
   return BL_OK;
 }
 

@@ -10,11 +10,25 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long CPU test")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    """A library context on cuda:0 bound to torch's current stream."""
+    import torch
+    from paper_1909_10286_amd import bl
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = bl.Context(0)
+    c.set_stream(torch.cuda.current_stream())
+    yield c
+    torch.cuda.synchronize()
+    c.close()
 
 
 @pytest.fixture(scope="session")
-def gpu_lib():
-    """The HIP library bound through ctypes; GPU tests fail loudly without it."""
-    from paper_1909_10286_amd import bl
-    return bl.load()
+def pool():
+    """Process pool running oracle candidate evaluations."""
+    from .oracle_pool import OraclePool
+    p = OraclePool()
+    yield p
+    p.close()

@@ -1,0 +1,140 @@
+"""Batched search (many uneven instances in one persistent launch), its
+autotuned schedule, and HIP-graph replays, against the oracle and against
+eager execution."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import init as OI
+from oracle import model as M
+from oracle import search as S
+from paper_1909_10286_amd import bl, inputs
+
+from .gpu_common import from_csr, to_csr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MEMBERS = [2, 9, 17, 33, 64, 101, 150]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _members(ctx, ks):
+    insts, ids, x0s = [], [], []
+    for k in ks:
+        inst = inputs.make_batch_instance(k, accept=OI.init_feasible)
+        x0 = OI.init_solution(inst)
+        iid = ctx.instance_upload(inst)
+        ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(x0))
+        insts.append(inst)
+        ids.append(iid)
+        x0s.append(x0)
+    return insts, ids, x0s
+
+
+def _rows(trace):
+    return [(r["it"], r["best_key"], r["cost_m"], r["makespan_s"], r["indicator"], r["use_best"])
+            for r in trace]
+
+
+def _orows(trace):
+    return [(r.it, r.best_key, r.cost_m, bl.INF_MAKESPAN if r.makespan_s == M.INF else r.makespan_s,
+             r.indicator, int(r.use_best)) for r in trace]
+
+
+def test_batch_members_match_oracle(ctx, pool):
+    """Every member's trajectory equals the oracle search of that instance
+    with Philox counter word = its position in the batch."""
+    _say("batch vs oracle")
+    insts, ids, x0s = _members(ctx, MEMBERS)
+    n, iters, thr = 512, 4, S.eps_threshold(0.5)
+    b = ctx.batch_create(ids, n)
+    ctx.batch_start(b, iters)
+    for _ in range(iters):
+        ctx.batch_step(b, 5, thr)
+    torch.cuda.synchronize()
+    for k, (inst, iid, x0) in enumerate(zip(insts, ids, x0s)):
+        st = S.search(inst, x0, 5, n, iters, thr, inst_idx=k, map_fn=pool)
+        assert _rows(ctx.search_trace(iid)) == _orows(st.trace), "member %d" % k
+        assert from_csr(ctx.solution_download(iid, bl.SLOT_BEST)) == st.x_best
+
+
+def _batch_traces(ctx, ks, n, iters, sched=None, graph_steps=0, autotune=None):
+    insts, ids, x0s = _members(ctx, ks)
+    b = ctx.batch_create(ids, n)
+    if sched:
+        ctx.batch_set_schedule(b, *sched)
+    ctx.batch_start(b, iters)
+    thr = S.eps_threshold(0.5)
+    if autotune is not None:
+        autotune["result"] = ctx.batch_autotune(b, 1, thr, autotune.get("path"))
+    if graph_steps:
+        g = ctx.batch_capture(b, 1, thr, graph_steps)
+        for r in range(iters // graph_steps):
+            ctx.graph_launch(g)
+            torch.cuda.synchronize()
+            torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    else:
+        for _ in range(iters):
+            ctx.batch_step(b, 1, thr)
+    torch.cuda.synchronize()
+    return [_rows(ctx.search_trace(i)) for i in ids]
+
+
+def test_batch_schedule_and_graph_do_not_change_results(ctx, tmp_path):
+    """Any schedule, the autotuned one, and graph replays give the eager
+    default-schedule trajectories bit for bit."""
+    _say("batch schedules / graph")
+    ks = [0, 5, 77, 120, 201, 255]
+    base = _batch_traces(ctx, ks, 4096, 6)
+    assert _batch_traces(ctx, ks, 4096, 6, sched=([64, 128, 65536], 0)) == base
+    assert _batch_traces(ctx, ks, 4096, 6, graph_steps=2) == base
+    cache = tmp_path / "sched.json"
+    info = {"path": str(cache)}
+    assert _batch_traces(ctx, ks, 4096, 6, autotune=info) == base
+    first = info["result"]
+    assert all(t in (256, 512, 1024, 2048, 4096) for t in first["tile"])
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    again = {"path": str(cache)}
+    _batch_traces(ctx, ks, 4096, 2, autotune=again)
+    assert again["result"] == first
+
+
+def test_search_graph_replays_match_eager(ctx):
+    """A captured 3-iteration graph replayed 3 times, with eager work and
+    synchronisation between replays, equals 9 eager iterations."""
+    _say("search graph")
+    inst = inputs.make_instance("mid100", 0, accept=OI.init_feasible)
+    x0 = OI.init_solution(inst)
+    thr = S.eps_threshold(0.5)
+    n = 1 << 14
+
+    def run(graph):
+        iid = ctx.instance_upload(inst)
+        ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(x0))
+        ctx.search_start(iid, 9)
+        if graph:
+            g = ctx.search_capture(iid, 3, thr, n, 3)
+            out = []
+            for _ in range(3):
+                ctx.graph_launch(g)
+                torch.cuda.synchronize()
+                torch.arange(100, device="cuda").cumsum(0).cpu()
+                out.append(_rows(ctx.search_trace(iid)))
+            return out
+        for _ in range(9):
+            ctx.search_step(iid, 3, thr, n)
+        torch.cuda.synchronize()
+        return _rows(ctx.search_trace(iid))
+    eager = run(False)
+    replays = run(True)
+    for r, rows in enumerate(replays):
+        assert rows == eager[:3 * (r + 1)]

@@ -28,16 +28,6 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
-    assert torch.cuda.is_available(), "GPU tests need a GPU"
-    c = bl.Context(0)
-    c.set_stream(torch.cuda.current_stream())
-    yield c
-    torch.cuda.synchronize()
-    c.close()
-
-
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
 
@@ -209,14 +199,6 @@ def test_select_best(ctx):
 
 # --------------------------------------------------------------- search ----
 
-@pytest.fixture(scope="module")
-def pool():
-    from .oracle_pool import OraclePool
-    p = OraclePool()
-    yield p
-    p.close()
-
-
 def _gpu_search(ctx, inst, x0, seed, n, iters, eps_thr, flags=0):
     iid = _setup(ctx, inst, x0, flags)
     ctx.search_start(iid, iters)
@@ -312,7 +294,6 @@ def test_full_size_iteration_sampled(ctx, pool, name, n, samples):
     ctx.select_best(d_key, n, d_best)
     torch.cuda.synchronize()
     assert int(d_best.cpu().numpy().view(np.uint64)[0]) == k
-    words = oracle_words(inst, base, 0, 0, 0, 0)  # empty: oracle draws below
     words = np.array([MV.encode(MV.draw_move(inst, base, 0, 0, int(i))) for i in idx], np.uint64)
     assert np.array_equal(d_mv.cpu().numpy().view(np.uint64)[idx], words)
     orc = oracle_batch(inst, base, words, st0.t_best)

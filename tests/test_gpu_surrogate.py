@@ -1,0 +1,136 @@
+"""The learned screen on the GPU (bf16 MFMA, fp32 accumulation) against the
+float64 reference in oracle/surrogate.py: predictions, summed gradients, and
+that Adam steps on the GPU reduce the loss."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import init as OI
+from oracle import model as M
+from oracle import moves as MV
+from oracle import search as S
+from oracle import surrogate as SG
+from paper_1909_10286_amd import bl, inputs
+
+from .gpu_common import to_csr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _flat(p):
+    return np.concatenate([p[k].reshape(-1) for k, _ in bl.SUR_SHAPES]).astype(np.float32)
+
+
+def _unflat(w):
+    out, k = {}, 0
+    for name, shape in bl.SUR_SHAPES:
+        n = int(np.prod(shape))
+        out[name] = np.asarray(w[k:k + n], dtype=np.float64).reshape(shape)
+        k += n
+    return out
+
+
+def _setup(ctx, name, wseed=3):
+    inst = inputs.make_instance(name, 0, accept=OI.init_feasible)
+    st = S.start(inst, OI.init_solution(inst))
+    base = st.x_best
+    iid = ctx.instance_upload(inst)
+    ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(base))
+    p = SG.init_params(inputs.surrogate_init_words(wseed))
+    rng = np.random.default_rng(wseed)
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    # Round the reference weights to float32, the precision the library keeps.
+    p = _unflat(_flat(p))
+    sur = ctx.sur_create(iid, _flat(p), float(st.cost_best), float(st.t_best), max_examples=512)
+    sc = SG.scales(inst, st.cost_best, st.t_best)
+    return inst, base, iid, sur, p, sc
+
+
+def _moves(inst, base, n, seed=7, feasible_only=True):
+    out = []
+    i = 0
+    while len(out) < n:
+        mv = MV.draw_move(inst, base, seed, 0, i)
+        i += 1
+        if feasible_only and not M.is_feasible(inst, MV.apply_move(base, mv)):
+            continue
+        out.append(mv)
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny12", "mid100", "clust500"])
+def test_predict_matches_float64_reference(ctx, name):
+    _say("surrogate predict", name)
+    inst, base, iid, sur, p, sc = _setup(ctx, name)
+    mvs = _moves(inst, base, 96)
+    words = np.array([MV.encode(m) for m in mvs], dtype=np.uint64)
+    d_mv = torch.from_numpy(words.view(np.int64)).cuda()
+    d_out = torch.empty(2 * len(mvs), dtype=torch.float32, device="cuda")
+    ctx.sur_predict(sur, d_mv, len(mvs), d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy().reshape(-1, 2).astype(np.float64)
+    ref = np.array([SG.predict(p, inst, MV.apply_move(base, m), sc) for m in mvs])
+    scale = np.abs(ref).max(axis=0)
+    err = np.abs(got - ref).max(axis=0)
+    assert (err <= 2e-2 * scale + 1e-3).all(), (err, scale)
+    # The ranking the screen relies on survives bf16: strong rank agreement.
+    rp = np.argsort(np.argsort(ref[:, 0]))
+    gp = np.argsort(np.argsort(got[:, 0]))
+    assert np.corrcoef(rp, gp)[0, 1] > 0.98
+
+
+@pytest.mark.parametrize("name", ["tiny12", "mid100"])
+def test_gradients_match_float64_reference(ctx, name):
+    _say("surrogate gradients", name)
+    inst, base, iid, sur, p, sc = _setup(ctx, name)
+    mvs = _moves(inst, base, 48, seed=11)
+    cost, mk = [], []
+    gref = {k: np.zeros(s) for k, s in bl.SUR_SHAPES}
+    lref = 0.0
+    for m in mvs:
+        ev = M.evaluate_solution(inst, MV.apply_move(base, m))
+        cost.append(ev.cost_m / 1000.0)
+        mk.append(ev.makespan_s)
+        l, g = SG.example_loss_and_grad(p, inst, MV.apply_move(base, m), sc, ev.cost_m, ev.makespan_s)
+        lref += l
+        for k in gref:
+            gref[k] += g[k]
+    words = np.array([MV.encode(m) for m in mvs], dtype=np.uint64)
+    d_mv = torch.from_numpy(words.view(np.int64)).cuda()
+    d_c = torch.tensor(cost, dtype=torch.float32, device="cuda")
+    d_m = torch.tensor(mk, dtype=torch.int32, device="cuda")
+    g, loss = ctx.sur_gradients(sur, d_mv, d_c, d_m, len(mvs))
+    gg = _unflat(g)
+    assert loss == pytest.approx(lref, rel=3e-2)
+    for k, _ in bl.SUR_SHAPES:
+        den = np.linalg.norm(gref[k])
+        rel = np.linalg.norm(gg[k] - gref[k]) / max(den, 1e-12)
+        assert rel <= 6e-2, (k, rel, den)
+
+
+def test_adam_steps_reduce_loss(ctx):
+    _say("surrogate training")
+    inst, base, iid, sur, p, sc = _setup(ctx, "mid100")
+    n = 512
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(iid, 5, 0, 0, 0, n, d_mv)
+    d_key = torch.empty(n, dtype=torch.int64, device="cuda")
+    d_c = torch.empty(n, dtype=torch.float32, device="cuda")
+    d_m = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.evaluate_batch(iid, d_mv, n, 1 << 40, d_key, d_c, d_m, None)
+    d_loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+    losses = []
+    for _ in range(60):
+        ctx.sur_train_step(sur, d_mv, d_c, d_m, n, d_loss)
+        l = d_loss.cpu().numpy()
+        losses.append(l[0] / max(l[1], 1))
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
