@@ -291,6 +291,59 @@ bl_status bl_sur_train_step(bl_ctx *ctx, int32_t sur, const uint64_t *d_moves,
                             const float *d_cost_km, const int32_t *d_makespan_s, uint32_t n,
                             float *d_loss);
 
+/*
+ * Learned screen (same surrogate, incremental inference).  The proposals of
+ * an iteration are the n_proposals draws of bl_search_step for the same
+ * seed, iteration and inst_index, taken against that iteration's base (the
+ * eq. (6) pick).  Each proposal changes the features of at most three fields,
+ * the pooled means of at most four BPs and the head inputs of at most two
+ * tours, so its prediction is the base's with those parts recomputed: three
+ * MLP rows per proposal instead of N_F.  A proposal is discarded when it
+ * breaks the donor BP's demand (eq. (2)) or when its predicted makespan
+ * exceeds the makespan gate, the incumbent makespan divided by t0_s plus
+ * mk_margin; the others are ranked by predicted path (normalised by c0_m),
+ * and the n_shortlist best (lowest index first among equal scores) form the
+ * shortlist.  Discarded proposals rank after all others.
+ */
+typedef struct {
+  uint32_t n_proposals;  /* 1 .. 2^24                                  */
+  uint32_t n_shortlist;  /* 1 .. n_proposals                           */
+  uint32_t n_fallback;   /* 0 .. 2^24 (screened step only)             */
+  float mk_margin;       /* added to the normalised makespan gate       */
+  float err_threshold;   /* screened step only, see below              */
+} bl_screen_params;
+
+/* Screen the proposals of the coming iteration of instance `inst` (the one
+ * the surrogate was created for; bl_search_start must have run) without
+ * taking the iteration.  d_shortlist: n_shortlist u32 proposal indices in
+ * ascending order (device, caller-owned).  d_score (nullable): n_proposals
+ * floats, the predicted normalised path, +inf for a discarded proposal.
+ * p->n is ignored.  Async. */
+bl_status bl_sur_screen(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
+                        const bl_screen_params *sc, uint32_t *d_shortlist, float *d_score);
+
+/* Screened search iteration: the iteration of bl_search_step (eq. (6) base
+ * pick, argmin, commit) with the argmin taken over the shortlist of
+ * bl_sur_screen, evaluated exactly.  The exact results also judge the
+ * screen: when no shortlisted candidate passes the exact gate, or the mean
+ * relative error of the predicted path over the shortlisted candidates that
+ * have an exact cost exceeds err_threshold, proposals 0 .. n_fallback-1 are
+ * evaluated exactly as well (the plain iteration) before the argmin.  Ties
+ * and the commit follow bl_search_step.  No host synchronisation.  p->n is
+ * ignored.  Async. */
+bl_status bl_sur_search_step(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
+                             const bl_screen_params *sc);
+
+typedef struct {
+  uint32_t iterations;   /* screened iterations run                    */
+  uint32_t fallbacks;    /* of which evaluated the fallback proposals  */
+  uint32_t last_used;    /* shortlisted candidates with an exact cost  */
+  float last_error;      /* last mean relative path error (+inf: none) */
+} bl_sur_stats;
+
+/* Counters of bl_sur_search_step.  Synchronising. */
+bl_status bl_sur_stats_get(bl_ctx *ctx, int32_t sur, bl_sur_stats *out);
+
 /* Kernel timing.  While enabled, every launch of the evaluation kernel made
  * by bl_search_step or bl_evaluate_batch is bracketed by two HIP events on
  * the context's stream.  bl_timing_read synchronises, returns the summed

@@ -59,6 +59,16 @@ class _SurConfig(C.Structure):
                 ("max_examples", C.c_uint32), ("c0_m", C.c_float), ("t0_s", C.c_float)]
 
 
+class _ScreenParams(C.Structure):
+    _fields_ = [("n_proposals", C.c_uint32), ("n_shortlist", C.c_uint32), ("n_fallback", C.c_uint32),
+                ("mk_margin", C.c_float), ("err_threshold", C.c_float)]
+
+
+class _SurStats(C.Structure):
+    _fields_ = [("iterations", C.c_uint32), ("fallbacks", C.c_uint32), ("last_used", C.c_uint32),
+                ("last_error", C.c_float)]
+
+
 class _Schedule(C.Structure):
     _fields_ = [("tile", C.c_uint32 * 3), ("order_policy", C.c_uint32)]
 
@@ -110,6 +120,11 @@ _SIGS = {
                                      C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
     "bl_sur_train_step": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_uint32, C.c_void_p]),
+    "bl_sur_screen": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams),
+                                  C.POINTER(_ScreenParams), C.c_void_p, C.c_void_p]),
+    "bl_sur_search_step": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams),
+                                       C.POINTER(_ScreenParams)]),
+    "bl_sur_stats_get": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SurStats)]),
     "bl_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "bl_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint32)]),
 }
@@ -385,6 +400,26 @@ class Context:
         self._check(self._lib.bl_sur_train_step(
             self._h, sur, C.c_void_p(_ptr(d_moves)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_mk)), n,
             C.c_void_p(_ptr(d_loss))))
+
+    def sur_screen(self, sur: int, seed: int, eps_threshold: int, n_proposals: int, n_shortlist: int,
+                   d_shortlist, d_score=None, mk_margin: float = 0.0, inst_index: int = 0):
+        p = _SearchParams(seed, eps_threshold, 0, inst_index)
+        sc = _ScreenParams(n_proposals, n_shortlist, 0, mk_margin, 0.0)
+        self._check(self._lib.bl_sur_screen(self._h, sur, C.byref(p), C.byref(sc),
+                                            C.c_void_p(_ptr(d_shortlist)), C.c_void_p(_ptr(d_score))))
+
+    def sur_search_step(self, sur: int, seed: int, eps_threshold: int, n_proposals: int,
+                        n_shortlist: int, n_fallback: int, mk_margin: float = 0.0,
+                        err_threshold: float = 0.05, inst_index: int = 0):
+        p = _SearchParams(seed, eps_threshold, 0, inst_index)
+        sc = _ScreenParams(n_proposals, n_shortlist, n_fallback, mk_margin, err_threshold)
+        self._check(self._lib.bl_sur_search_step(self._h, sur, C.byref(p), C.byref(sc)))
+
+    def sur_stats(self, sur: int) -> dict:
+        s = _SurStats()
+        self._check(self._lib.bl_sur_stats_get(self._h, sur, C.byref(s)))
+        return dict(iterations=s.iterations, fallbacks=s.fallbacks, last_used=s.last_used,
+                    last_error=s.last_error)
 
 
 SUR_PARAMS = 27586

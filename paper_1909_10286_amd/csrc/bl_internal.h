@@ -140,6 +140,44 @@ struct SurDev {
   float *loss;                        // [2] loss sum, examples counted
 };
 
+// Screening of proposals through the learned screen.
+struct ScreenDesc {          // what one proposal changes relative to the base (64 bytes)
+  uint16_t f[3];             // fields whose features change (0xFFFF: none)
+  uint16_t bold[3];          // their BP in the base
+  uint16_t bnew[3];          // their BP in the candidate
+  uint16_t ab[4];            // BPs whose pooled embedding changes (0xFFFF: none)
+  int16_t dcnt[4];           // change of their field counts
+  uint16_t tg[2];            // tours whose head input changes (0xFFFF: none)
+  int16_t dnf[2], dnb[2];    // change of the tours' field and BP counts
+  float u6[2];               // new return-leg feature of those tours
+  uint16_t moved_bp;         // BP move: the BP (0xFFFF otherwise)
+  uint16_t dst_tour;         // BP move: its destination tour
+  uint8_t feasible, pad[5];
+};
+
+struct ScreenDev {
+  float *baseP;              // [NF][64] projected base rows, by base position
+  float *Q;                  // [NB][64] sums of the base rows per BP
+  float *R;                  // [NT][64] sums over the tour's BPs of the BP means
+  float *U;                  // [NT][64] b3 + tour features through W3 rows 128..135
+  float *ub6;                // [NT] base return-leg feature
+  float *yb;                 // [NT][2] base head outputs
+  int32_t *nbg, *nfg, *tstart, *tend;  // [NT] BP / field counts, position range
+  uint32_t *bsupply;         // [NB] supply of the base's fields per BP, kg
+  float *scal;               // [4]: predicted base path, top-3 base completion outputs
+  int32_t *top_g;            // [3] tours of those top-3 outputs
+  ScreenDesc *desc;          // [chunk]
+  uint32_t *keys;            // [n_prop] order-preserving score bits (0xFFFFFFFF: discarded)
+  uint32_t *hist;            // [2048]
+  uint32_t *sel;             // [8] radix-select state
+  uint32_t *blk;             // [2 * 1024] per-block counts / offsets
+  uint32_t *short_idx;       // [k] shortlisted proposal indices
+  uint64_t *short_key;       // [k] their exact keys
+  float *short_cost;         // [k] their exact costs, km
+  uint32_t *flag;            // [1] 1: evaluate the plain fallback batch
+  float *stats;              // [4]: mean relative error, fallbacks, screened iterations, used
+};
+
 // Kernel entry points (launch wrappers defined in eval.hip).
 hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t eps_thr,
                           uint32_t inst_index, hipStream_t s);
@@ -149,7 +187,11 @@ hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
                              uint8_t *flags, int grid, hipStream_t s);
 hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
-                              uint32_t inst_index, int grid, hipStream_t s);
+                              uint32_t inst_index, int grid, hipStream_t s,
+                              const uint32_t *run_flag = nullptr);
+hipError_t launch_eval_gather(const InstParams &P, uint64_t seed, const uint32_t *idx, uint32_t n,
+                              uint32_t inst_index, uint64_t *key, float *cost, int grid,
+                              hipStream_t s);
 hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t inst_index,
                          hipStream_t s);
 hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStream_t s);
@@ -178,6 +220,13 @@ hipError_t launch_sur_backward(const InstParams &P, const SurDev &S, uint32_t n,
                                hipStream_t s);
 hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float eps, float scale,
                            uint32_t step, hipStream_t s);
+
+hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
+                         uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
+                         uint32_t chunk, int n_cu, hipStream_t s);
+hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s);
+hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,
+                            float err_thr, hipStream_t s);
 
 enum { kPrepFromBase = 0, kPrepSearch = 1 };
 enum { kCommitStart = 0, kCommitStep = 1 };

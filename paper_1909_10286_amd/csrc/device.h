@@ -574,7 +574,7 @@ __host__ __device__ __forceinline__ uint32_t round4(uint32_t w) { return (w + 3u
 extern __shared__ uint4 g_lds4[];
 
 // ----------------------------------------------------------- kernels ----
-enum { kModeBatch = 0, kModeSearch = 1 };
+enum { kModeBatch = 0, kModeSearch = 1, kModeGather = 2 };
 
 struct CandResult {
   uint64_t key;

@@ -27,13 +27,20 @@ namespace bl {
 
 namespace {
 
+// Modes: batch (move records given, per-candidate outputs), search (moves
+// drawn for indices 0..n-1, argmin into the instance's slot) and gather
+// (moves drawn for the indices listed in `gather`, per-entry outputs and the
+// argmin).  `run_flag` (nullable): the launch does nothing while it is 0.
 template <bool DLDS, int MODE>
 __global__ __launch_bounds__(256) void k_eval(InstParams P, const uint64_t *__restrict__ moves,
                                               uint32_t n, int64_t t_star_arg, uint64_t seed,
                                               uint32_t inst_index, uint64_t *__restrict__ out_key,
                                               float *__restrict__ out_cost,
                                               int32_t *__restrict__ out_mk,
-                                              uint8_t *__restrict__ out_flags) {
+                                              uint8_t *__restrict__ out_flags,
+                                              const uint32_t *__restrict__ gather,
+                                              const uint32_t *__restrict__ run_flag) {
+  if (run_flag && *run_flag == 0u) return;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   const uint32_t img_words = round4(P.lay.total_words);
   stage(lds, P.image, P.lay.total_words);
@@ -54,23 +61,24 @@ __global__ __launch_bounds__(256) void k_eval(InstParams P, const uint64_t *__re
 
   uint32_t it = 0;
   int64_t t_star = t_star_arg;
-  if (MODE == kModeSearch) {
+  if (MODE != kModeBatch) {
     it = P.st->it;
     t_star = P.st->t_best;
   }
   uint64_t best = kInfKey;
   for (uint32_t c = gseg; c < n; c += nseg) {
-    const uint64_t w = MODE == kModeSearch ? draw_move(seed, c, it, inst_index, V, P) : moves[c];
-    const CandResult r = eval_one(V, P, w, c, t, S, seg_base, seg_mask, t_star);
-    if (MODE == kModeBatch && t == 0) {
-      out_key[c] = r.key;
+    const uint32_t ci = MODE == kModeGather ? gather[c] : c;
+    const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
+    const CandResult r = eval_one(V, P, w, ci, t, S, seg_base, seg_mask, t_star);
+    if (MODE != kModeSearch && t == 0) {
+      if (out_key) out_key[c] = r.key;
       if (out_cost) out_cost[c] = r.cost_km;
       if (out_mk) out_mk[c] = r.mk;
       if (out_flags) out_flags[c] = (uint8_t)r.flags;
     }
     best = r.key < best ? r.key : best;
   }
-  if (MODE == kModeSearch) wave_min_to(best, P.best_key);
+  if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
 
 // Base preparation: optional eq. (6) pick (copy x* or x_old to the base
@@ -470,23 +478,38 @@ hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_
   const size_t lds = eval_lds_bytes(P);
   if (P.d_in_lds)
     hipLaunchKernelGGL((k_eval<true, kModeBatch>), dim3(grid), dim3(256), lds, s, P, moves, n,
-                       t_star, 0ull, 0u, key, cost, mk, flags);
+                       t_star, 0ull, 0u, key, cost, mk, flags, nullptr, nullptr);
   else
     hipLaunchKernelGGL((k_eval<false, kModeBatch>), dim3(grid), dim3(256), lds, s, P, moves, n,
-                       t_star, 0ull, 0u, key, cost, mk, flags);
+                       t_star, 0ull, 0u, key, cost, mk, flags, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
-                              uint32_t inst_index, int grid, hipStream_t s) {
+                              uint32_t inst_index, int grid, hipStream_t s,
+                              const uint32_t *run_flag) {
   if (n == 0) return hipSuccess;
   const size_t lds = eval_lds_bytes(P);
   if (P.d_in_lds)
     hipLaunchKernelGGL((k_eval<true, kModeSearch>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr);
+                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr, nullptr, run_flag);
   else
     hipLaunchKernelGGL((k_eval<false, kModeSearch>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr);
+                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr, nullptr, run_flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_gather(const InstParams &P, uint64_t seed, const uint32_t *idx, uint32_t n,
+                              uint32_t inst_index, uint64_t *key, float *cost, int grid,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = eval_lds_bytes(P);
+  if (P.d_in_lds)
+    hipLaunchKernelGGL((k_eval<true, kModeGather>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
+                       0ll, seed, inst_index, key, cost, nullptr, nullptr, idx, nullptr);
+  else
+    hipLaunchKernelGGL((k_eval<false, kModeGather>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
+                       0ll, seed, inst_index, key, cost, nullptr, nullptr, idx, nullptr);
   return hipGetLastError();
 }
 

@@ -50,6 +50,9 @@ struct Sur {
   SurDev D{};
   std::vector<void *> allocs;
   uint32_t step = 0;
+  ScreenDev T{};                 // screening buffers, allocated on first use
+  std::vector<void *> t_allocs;
+  uint32_t t_nprop = 0, t_k = 0, t_chunk = 0;
 };
 
 struct Batch {
@@ -451,6 +454,10 @@ void bl_destroy(bl_ctx *ctx) {
   for (auto &B : ctx->batches) {
     (void)hipFree(B->d_inst);
     (void)hipFree(B->d_sched);
+  }
+  for (auto &S : ctx->surs) {
+    for (void *p : S->allocs) (void)hipFree(p);
+    for (void *p : S->t_allocs) (void)hipFree(p);
   }
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
@@ -1242,6 +1249,143 @@ bl_status bl_sur_train_step(bl_ctx *c, int32_t id, const uint64_t *d_moves, cons
   HIP_TRY(c, launch_sur_adam(S->D, g.lr, g.beta1, g.beta2, g.adam_eps, 1.f / (float)n, S->step, c->stream));
   HIP_TRY(c, launch_sur_pack(S->D, c->stream));
   if (d_loss) HIP_TRY(c, hipMemcpyAsync(d_loss, S->D.loss, 8, hipMemcpyDeviceToDevice, c->stream));
+  return BL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <class T>
+bl_status scr_alloc(bl_ctx *c, Sur &S, T *&p, size_t n) {
+  void *q = nullptr;
+  HIP_TRY(c, hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+  S.t_allocs.push_back(q);
+  p = (T *)q;
+  return BL_OK;
+}
+
+bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, uint32_t k) {
+  // Proposals are screened in chunks whose three changed rows each fit the
+  // surrogate's example buffers (max_examples * NF rows).
+  const uint32_t lim = S.D.cap_ex * (uint32_t)I.NF / 3u;
+  if (lim == 0) return fail(c, BL_EINVAL, "max_examples * n_fields < 3: no room for screening rows");
+  uint32_t chunk = std::min(nprop, lim);
+  if (chunk >= 256u) chunk &= ~255u;
+  if (S.T.keys && S.t_nprop >= nprop && S.t_k >= k && S.t_chunk >= chunk) return BL_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (void *p : S.t_allocs) (void)hipFree(p);
+  S.t_allocs.clear();
+  ScreenDev &T = S.T;
+  const size_t NF = I.NF, NB = I.NB, NT = I.NT;
+  bl_status st = BL_OK;
+  if ((st = scr_alloc(c, S, T.baseP, NF * kSurA)) || (st = scr_alloc(c, S, T.Q, NB * kSurA)) ||
+      (st = scr_alloc(c, S, T.R, NT * kSurA)) || (st = scr_alloc(c, S, T.U, NT * kSurA)) ||
+      (st = scr_alloc(c, S, T.ub6, NT)) || (st = scr_alloc(c, S, T.yb, 2 * NT)) ||
+      (st = scr_alloc(c, S, T.nbg, NT)) || (st = scr_alloc(c, S, T.nfg, NT)) ||
+      (st = scr_alloc(c, S, T.tstart, NT)) || (st = scr_alloc(c, S, T.tend, NT)) ||
+      (st = scr_alloc(c, S, T.bsupply, NB)) || (st = scr_alloc(c, S, T.scal, 4)) ||
+      (st = scr_alloc(c, S, T.top_g, 3)) || (st = scr_alloc(c, S, T.desc, chunk)) ||
+      (st = scr_alloc(c, S, T.keys, nprop)) || (st = scr_alloc(c, S, T.hist, 2048)) ||
+      (st = scr_alloc(c, S, T.sel, 8)) || (st = scr_alloc(c, S, T.blk, 2048)) ||
+      (st = scr_alloc(c, S, T.short_idx, k)) || (st = scr_alloc(c, S, T.short_key, k)) ||
+      (st = scr_alloc(c, S, T.short_cost, k)) || (st = scr_alloc(c, S, T.flag, 1)) ||
+      (st = scr_alloc(c, S, T.stats, 4))) {
+    for (void *p : S.t_allocs) (void)hipFree(p);
+    S.t_allocs.clear();
+    S.T = ScreenDev{};
+    return st;
+  }
+  HIP_TRY(c, hipMemset(T.stats, 0, 16));
+  HIP_TRY(c, hipMemset(T.flag, 0, 4));
+  S.t_nprop = nprop;
+  S.t_k = k;
+  S.t_chunk = chunk;
+  return BL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+}  // extern "C"
+
+namespace {
+
+// Validation, buffers, base pick and screen of one iteration's proposals.
+bl_status screen_on(bl_ctx *c, Sur *S, const bl_search_params *p, const bl_screen_params *sc,
+                    Instance *&I, hipStream_t &q) {
+  if (!S) return fail(c, BL_EINVAL, "bad surrogate id");
+  I = c->inst[S->inst].get();
+  if (!p || !sc) return fail(c, BL_EINVAL, "null params");
+  if (!I->started) return fail(c, BL_ESTATE, "bl_search_start not called");
+  if (sc->n_proposals == 0 || sc->n_proposals > kMaxCand)
+    return fail(c, BL_EINVAL, "n_proposals out of 1..2^24");
+  if (sc->n_shortlist == 0 || sc->n_shortlist > sc->n_proposals)
+    return fail(c, BL_EINVAL, "n_shortlist out of 1..n_proposals");
+  if (sc->n_fallback > kMaxCand) return fail(c, BL_EINVAL, "n_fallback > 2^24");
+  if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (c->capturing && !(S->T.keys && S->t_nprop >= sc->n_proposals && S->t_k >= sc->n_shortlist))
+    return fail(c, BL_ESTATE, "run one screened call of this size before capturing it");
+  bl_status st = screen_buffers(c, *S, *I, sc->n_proposals, sc->n_shortlist);
+  if (st != BL_OK) return st;
+  const uint32_t chunk = std::min(S->t_chunk, sc->n_proposals);
+  q = work_stream(c);
+  HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
+  HIP_TRY(c, launch_screen(I->P, S->D, S->T, p->seed, p->inst_index, sc->n_proposals, sc->n_shortlist,
+                           sc->mk_margin, chunk, c->n_cu, q));
+  return BL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bl_status bl_sur_screen(bl_ctx *c, int32_t id, const bl_search_params *p, const bl_screen_params *sc,
+                        uint32_t *d_shortlist, float *d_score) {
+  if (!d_shortlist) return fail(c, BL_EINVAL, "null shortlist buffer");
+  Sur *S = get_sur(c, id);
+  Instance *I = nullptr;
+  hipStream_t q = nullptr;
+  bl_status st = screen_on(c, S, p, sc, I, q);
+  if (st != BL_OK) return st;
+  HIP_TRY(c, hipMemcpyAsync(d_shortlist, S->T.short_idx, (size_t)sc->n_shortlist * 4,
+                            hipMemcpyDeviceToDevice, q));
+  if (d_score) HIP_TRY(c, launch_scr_export(S->T, sc->n_proposals, d_score, q));
+  return BL_OK;
+}
+
+bl_status bl_sur_search_step(bl_ctx *c, int32_t id, const bl_search_params *p,
+                             const bl_screen_params *sc) {
+  Sur *S = get_sur(c, id);
+  Instance *I = nullptr;
+  hipStream_t q = nullptr;
+  bl_status st = screen_on(c, S, p, sc, I, q);
+  if (st != BL_OK) return st;
+  HIP_TRY(c, launch_eval_gather(I->P, p->seed, S->T.short_idx, sc->n_shortlist, p->inst_index,
+                                S->T.short_key, S->T.short_cost, grid_for(c, *I, sc->n_shortlist, true), q));
+  HIP_TRY(c, launch_scr_check(I->P, S->D, S->T, sc->n_shortlist, sc->err_threshold, q));
+  if (sc->n_fallback)
+    HIP_TRY(c, launch_eval_search(I->P, p->seed, sc->n_fallback, p->inst_index,
+                                  grid_for(c, *I, sc->n_fallback, true), q, S->T.flag));
+  HIP_TRY(c, launch_commit(I->P, kCommitStep, p->seed, p->inst_index, q));
+  return BL_OK;
+}
+
+bl_status bl_sur_stats_get(bl_ctx *c, int32_t id, bl_sur_stats *out) {
+  Sur *S = get_sur(c, id);
+  if (!S || !out) return fail(c, BL_EINVAL, "bad surrogate or null output");
+  *out = bl_sur_stats{0, 0, 0, 0.f};
+  if (!S->T.stats) return BL_OK;
+  float st[4];
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(st, S->T.stats, 16, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  out->iterations = (uint32_t)st[2];
+  out->fallbacks = (uint32_t)st[1];
+  out->last_used = (uint32_t)st[3];
+  out->last_error = st[0];
   return BL_OK;
 }
 

@@ -526,6 +526,569 @@ __global__ void k_sur_zero(float *p, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
+// ------------------------------------------------------------- screening --
+// A proposal changes the features of at most three fields (the moved field
+// or the moved BP's first field, and the fields whose route predecessor
+// changes), the pooled means of at most four BPs and the head inputs of at
+// most two tours.  Its prediction is the base's with those parts replaced.
+
+// Order-preserving bits of a float score (smaller score, smaller key).
+__device__ __forceinline__ uint32_t score_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_score(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// Base tables from the base's forward rows (example 0); one wave, lane c =
+// column c.
+__global__ void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
+  const View V = make_view(P.image, P.lay, P.dist);
+  const int c = threadIdx.x & 63;
+  for (int q = 0; q < P.NF; ++q) T.baseP[q * kSurA + c] = S.P[q * kSurA + c];
+  for (int b = 0; b < P.NB; ++b) {
+    float s = 0.f;
+    const int st = V.bp_start[b], len = V.bp_len[b];
+    for (int q = st; q < st + len; ++q) s += S.P[q * kSurA + c];
+    T.Q[b * kSurA + c] = s;
+  }
+  float w3u[kSurU];
+  for (int j = 0; j < kSurU; ++j) w3u[j] = S.W[kSurOffW3 + (kSurH + j) * kSurA + c];
+  const float b3 = S.W[kSurOffB3 + c];
+  const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
+  const float b40 = S.W[kSurOffB4], b41 = S.W[kSurOffB4 + 1];
+  float psum = 0.f;
+  for (int g = 0; g < P.NT; ++g) {
+    const int nb = tour_len(V, g);
+    float R = 0.f;
+    int nf = 0;
+    for (int j = 0; j < nb; ++j) {
+      const int b = V.tour_bp[V.tour_off[g] + j];
+      const int len = V.bp_len[b];
+      nf += len;
+      if (len > 0) R += T.Q[b * kSurA + c] / (float)len;
+    }
+    const float *u = S.ex_u + (size_t)g * kSurU;
+    float U = b3;
+    for (int j = 0; j < kSurU; ++j) U += u[j] * w3u[j];
+    const float a = fmaxf((nb > 0 ? R / (float)nb : 0.f) + U, 0.f);
+    const float y0 = wave_sum(a * w40) + b40, y1 = wave_sum(a * w41) + b41;
+    T.R[g * kSurA + c] = R;
+    T.U[g * kSurA + c] = U;
+    if (c == 0) {
+      T.yb[2 * g] = y0;
+      T.yb[2 * g + 1] = y1;
+      T.nbg[g] = nb;
+      T.nfg[g] = nf;
+      T.ub6[g] = u[6];
+      if (nf > 0) psum += y0;
+    }
+  }
+  if (c == 0) {
+    int run = 0;
+    for (int g = 0; g < P.NT; ++g) {
+      T.tstart[g] = run;
+      run += T.nfg[g];
+      T.tend[g] = run;
+    }
+    // Three largest completion outputs over active tours (ties to the lower tour).
+    int tg[3] = {-1, -1, -1};
+    for (int k = 0; k < 3; ++k)
+      for (int g = 0; g < P.NT; ++g) {
+        if (T.nfg[g] == 0 || g == tg[0] || g == tg[1]) continue;
+        if (tg[k] < 0 || T.yb[2 * g + 1] > T.yb[2 * tg[k] + 1]) tg[k] = g;
+      }
+    T.scal[0] = psum;
+    for (int k = 0; k < 3; ++k) {
+      T.top_g[k] = tg[k];
+      T.scal[1 + k] = tg[k] >= 0 ? T.yb[2 * tg[k] + 1] : 0.f;
+    }
+  }
+  for (int b = c; b < P.NB; b += 64) {
+    uint32_t s = 0;
+    for (int q = V.bp_start[b]; q < V.bp_start[b] + V.bp_len[b]; ++q) s += V.supply[V.seq[q]];
+    T.bsupply[b] = s;
+  }
+}
+
+__device__ __forceinline__ void feature_row(const View &V, const InstParams &P, const SurDev &S,
+                                            uint16_t *dst, int f, int b, int pred) {
+  const int nb1 = 1 + P.NB;
+  const size_t Vn = (size_t)P.V;
+  const float *fs = S.fstat + (size_t)f * 8;
+  const uint32_t dfb = V.D[(size_t)(nb1 + f) * Vn + 1 + b];
+  const uint32_t leg = pred < 0 ? V.dhq[f] : V.D[(size_t)(nb1 + pred) * Vn + nb1 + f];
+  float v[16] = {fs[0], fs[1], fs[2], fs[3], S.bxy[2 * b], S.bxy[2 * b + 1],
+                 (float)dfb * S.inv_ds, (float)leg * S.inv_ds, fs[5] * (float)dfb, fs[4],
+                 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  write_row(dst, v);
+}
+
+__device__ __forceinline__ void add_bp(ScreenDesc &d, int b, int dc) {
+  for (int a = 0; a < 4; ++a) {
+    if (d.ab[a] == (uint16_t)b) {
+      d.dcnt[a] += (int16_t)dc;
+      return;
+    }
+    if (d.ab[a] == 0xFFFF) {
+      d.ab[a] = (uint16_t)b;
+      d.dcnt[a] = (int16_t)dc;
+      return;
+    }
+  }
+}
+
+// Descriptor and changed feature rows (3 per proposal) of proposals
+// i0 .. i0 + cnt - 1, one thread each.
+__global__ __launch_bounds__(256) void k_scr_rows(InstParams P, SurDev S, ScreenDev T, uint64_t seed,
+                                                  uint32_t inst_index, uint32_t i0, uint32_t cnt) {
+  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
+  stage(lds, P.image, P.lay.total_words);
+  __syncthreads();
+  const View V = make_view(lds, P.lay, P.dist);
+  const uint32_t it = P.st->it;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+    const Move m = decode_move(draw_move(seed, i0 + j, it, inst_index, V, P), V, P);
+    ScreenDesc d;
+    for (int k = 0; k < 3; ++k) d.f[k] = d.bold[k] = d.bnew[k] = 0xFFFF;
+    for (int k = 0; k < 4; ++k) {
+      d.ab[k] = 0xFFFF;
+      d.dcnt[k] = 0;
+    }
+    d.tg[0] = d.tg[1] = 0xFFFF;
+    d.dnf[0] = d.dnf[1] = d.dnb[0] = d.dnb[1] = 0;
+    d.u6[0] = d.u6[1] = 0.f;
+    d.moved_bp = d.dst_tour = 0xFFFF;
+    d.feasible = 1;
+    for (int k = 0; k < 5; ++k) d.pad[k] = 0;
+    int rf[3] = {-1, -1, -1}, rb[3] = {0, 0, 0}, rp[3] = {-1, -1, -1};
+    int Ts, Td, newlast_d = -2, newlast_s = -2;  // -2: unchanged, -1: tour empty
+    if (m.kind == 0) {
+      const int f = m.v, bs = m.src, bd = m.dst, r = m.r, s = m.slot;
+      Ts = V.bp_tour[bs];
+      Td = V.bp_tour[bd];
+      const int qf = V.pos[f];
+      if (bs != bd && T.bsupply[bs] - V.supply[f] < V.demand[bs]) d.feasible = 0;
+      const int pold = qf - 1 >= T.tstart[Ts] ? V.seq[qf - 1] : -1;
+      const int nold = qf + 1 < T.tend[Ts] ? V.seq[qf + 1] : -1;
+      const int room = V.bp_len[bd] - (bd == bs ? 1 : 0);
+      int pnew, nnew;
+      if (s > 0) {
+        int k = s - 1;
+        if (bd == bs && k >= r) ++k;
+        pnew = V.seq[V.bp_start[bd] + k];
+      } else {
+        int pp = V.bp_start[bd] - 1;
+        if (pp == qf) --pp;
+        pnew = pp >= T.tstart[Td] ? V.seq[pp] : -1;
+      }
+      if (s < room) {
+        int k = s;
+        if (bd == bs && k >= r) ++k;
+        nnew = V.seq[V.bp_start[bd] + k];
+      } else {
+        int pp = V.bp_start[bd] + V.bp_len[bd];
+        if (pp == qf) ++pp;
+        nnew = pp < T.tend[Td] ? V.seq[pp] : -1;
+      }
+      rf[0] = f;
+      rb[0] = bd;
+      rp[0] = pnew;
+      d.bold[0] = (uint16_t)bs;
+      if (nnew >= 0) {
+        rf[1] = nnew;
+        rb[1] = V.fbp[nnew];
+        rp[1] = f;
+        d.bold[1] = (uint16_t)rb[1];
+      }
+      if (nold >= 0 && nold != nnew) {
+        rf[2] = nold;
+        rb[2] = V.fbp[nold];
+        rp[2] = pold;
+        d.bold[2] = (uint16_t)rb[2];
+      }
+      add_bp(d, bs, bs == bd ? 0 : -1);
+      add_bp(d, bd, bs == bd ? 0 : 1);
+      if (Ts != Td) {
+        d.dnf[0] = -1;
+        d.dnf[1] = 1;
+      }
+      if (nnew < 0) newlast_d = f;
+      if (nold < 0) newlast_s = pold;
+    } else {
+      const int b = m.v, s = m.slot, r = m.r;
+      Ts = m.src;
+      Td = m.dst;
+      d.moved_bp = (uint16_t)b;
+      d.dst_tour = (uint16_t)Td;
+      add_bp(d, b, 0);
+      const int bs0 = V.bp_start[b], len = V.bp_len[b], bs1 = bs0 + len;
+      if (Ts != Td) {
+        d.dnf[0] = (int16_t)-len;
+        d.dnf[1] = (int16_t)len;
+        d.dnb[0] = -1;
+        d.dnb[1] = 1;
+      }
+      if (len > 0) {
+        const int pold = bs0 - 1 >= T.tstart[Ts] ? V.seq[bs0 - 1] : -1;
+        const int nold = bs1 < T.tend[Ts] ? V.seq[bs1] : -1;
+        const int room = tour_len(V, Td) - (Td == Ts ? 1 : 0);
+        int ip;
+        if (s < room) {
+          int jj = s;
+          if (Td == Ts && jj >= r) ++jj;
+          ip = V.bp_start[V.tour_bp[V.tour_off[Td] + jj]];
+        } else {
+          ip = T.tend[Td];
+        }
+        int pp = ip - 1;
+        if (pp >= bs0 && pp < bs1) pp = bs0 - 1;
+        const int pnew = pp >= T.tstart[Td] ? V.seq[pp] : -1;
+        pp = ip;
+        if (pp >= bs0 && pp < bs1) pp = bs1;
+        const int nnew = pp < T.tend[Td] ? V.seq[pp] : -1;
+        rf[0] = V.seq[bs0];
+        rb[0] = b;
+        rp[0] = pnew;
+        d.bold[0] = (uint16_t)b;
+        if (nnew >= 0) {
+          rf[1] = nnew;
+          rb[1] = V.fbp[nnew];
+          rp[1] = V.seq[bs1 - 1];
+          d.bold[1] = (uint16_t)rb[1];
+        }
+        if (nold >= 0 && nold != nnew) {
+          rf[2] = nold;
+          rb[2] = V.fbp[nold];
+          rp[2] = pold;
+          d.bold[2] = (uint16_t)rb[2];
+        }
+        if (nnew < 0) newlast_d = V.seq[bs1 - 1];
+        if (nold < 0) newlast_s = pold;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint16_t *row = S.phi + ((size_t)j * 3 + k) * kSurK1;
+      if (rf[k] >= 0) {
+        d.f[k] = (uint16_t)rf[k];
+        d.bnew[k] = (uint16_t)rb[k];
+        add_bp(d, rb[k], 0);
+        add_bp(d, d.bold[k], 0);
+        feature_row(V, P, S, row, rf[k], rb[k], rp[k]);
+      } else {
+        float z[16] = {0.f};
+        write_row(row, z);
+      }
+    }
+    // Affected tours and their new return legs.
+    auto last_feat = [&](int g, int nl) -> float {
+      if (nl == -2) return T.ub6[g];
+      return nl >= 0 ? (float)V.dhq[nl] * S.inv_ds : 0.f;
+    };
+    if (Ts == Td) {
+      d.tg[0] = (uint16_t)Ts;
+      d.dnf[0] = 0;
+      d.dnb[0] = 0;
+      d.u6[0] = last_feat(Ts, newlast_d != -2 ? newlast_d : newlast_s);
+    } else {
+      d.tg[0] = (uint16_t)Ts;
+      d.tg[1] = (uint16_t)Td;
+      d.u6[0] = last_feat(Ts, newlast_s);
+      d.u6[1] = last_feat(Td, newlast_d);
+    }
+    T.desc[j] = d;
+  }
+}
+
+// Predicted (path, makespan) of proposals i0 .. i0+cnt-1 from their
+// descriptors and projected rows; writes their score keys (predicted path,
+// or discarded when infeasible or above the makespan gate).
+__global__ __launch_bounds__(256) void k_scr_score(InstParams P, SurDev S, ScreenDev T, uint32_t i0,
+                                                   uint32_t cnt, float mk_margin) {
+  const View V = make_view(P.image, P.lay, P.dist);
+  const float gate = (float)P.st->t_best * S.inv_t0 + mk_margin;
+  const float b40 = S.W[kSurOffB4], b41 = S.W[kSurOffB4 + 1];
+  const float inv_nf = 1.f / (float)P.NF, inv_nb = 1.f / (float)P.NB;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+    const ScreenDesc d = T.desc[j];
+    uint32_t key = 0xFFFFFFFFu;
+    if (d.feasible) {
+      float y0[2] = {b40, b40}, y1[2] = {b41, b41};
+      int bt[4], ct[4], cb[4], cn[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int b = d.ab[a];
+        bt[a] = ct[a] = -1;
+        cb[a] = cn[a] = 0;
+        if (b != 0xFFFF) {
+          bt[a] = V.bp_tour[b];
+          ct[a] = b == d.moved_bp ? d.dst_tour : bt[a];
+          cb[a] = V.bp_len[b];
+          cn[a] = cb[a] + d.dcnt[a];
+        }
+      }
+      int qpos[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qpos[k] = d.f[k] != 0xFFFF ? V.pos[d.f[k]] : 0;
+      const float *pr = S.P + (size_t)j * 3 * kSurA;
+      for (int c = 0; c < kSurA; ++c) {
+        float eo[4], en[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          eo[a] = en[a] = 0.f;
+          if (bt[a] < 0) continue;
+          const int b = d.ab[a];
+          const float qo = T.Q[b * kSurA + c];
+          float qn = qo;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            if (d.f[k] == 0xFFFF) continue;
+            if (d.bold[k] == b) qn -= T.baseP[qpos[k] * kSurA + c];
+            if (d.bnew[k] == b) qn += pr[k * kSurA + c];
+          }
+          eo[a] = cb[a] > 0 ? qo / (float)cb[a] : 0.f;
+          en[a] = cn[a] > 0 ? qn / (float)cn[a] : 0.f;
+        }
+        const float w3u4 = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c];
+        const float w3u5 = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c];
+        const float w3u6 = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
+        const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          if (d.tg[tt] == 0xFFFF) continue;
+          const int g = d.tg[tt];
+          float R = T.R[g * kSurA + c];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            if (bt[a] == g) R -= eo[a];
+            if (ct[a] == g) R += en[a];
+          }
+          const int nbn = T.nbg[g] + d.dnb[tt];
+          const float z = (nbn > 0 ? R / (float)nbn : 0.f) + T.U[g * kSurA + c] +
+                          (float)d.dnf[tt] * inv_nf * w3u4 + (float)d.dnb[tt] * inv_nb * w3u5 +
+                          (d.u6[tt] - T.ub6[g]) * w3u6;
+          const float a = fmaxf(z, 0.f);
+          y0[tt] += a * w40;
+          y1[tt] += a * w41;
+        }
+      }
+      float pp = T.scal[0];
+      float mm = -__builtin_inff();
+      for (int k = 0; k < 3; ++k) {
+        const int g = T.top_g[k];
+        if (g >= 0 && g != d.tg[0] && g != d.tg[1]) {
+          mm = T.scal[1 + k];
+          break;
+        }
+      }
+      for (int tt = 0; tt < 2; ++tt) {
+        if (d.tg[tt] == 0xFFFF) continue;
+        const int g = d.tg[tt];
+        if (T.nfg[g] > 0) pp -= T.yb[2 * g];
+        if (T.nfg[g] + d.dnf[tt] > 0) {
+          pp += y0[tt];
+          mm = fmaxf(mm, y1[tt]);
+        }
+      }
+      if (mm <= gate) key = score_key(pp);
+    }
+    T.keys[i0 + j] = key;
+  }
+}
+
+// Radix selection of the k smallest score keys (three digit passes of
+// 11, 11 and 10 bits), then an order-preserving compaction: every key below
+// the k-th and the lowest-index ties at it.
+__global__ void k_topk_hist(const uint32_t *keys, uint32_t n, int pass, const uint32_t *sel,
+                            uint32_t *hist) {
+  __shared__ uint32_t h[2048];
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint32_t p1 = sel[0], p12 = (sel[0] << 11) | sel[1];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (pass == 0)
+      atomicAdd(&h[k >> 21], 1u);
+    else if (pass == 1) {
+      if ((k >> 21) == p1) atomicAdd(&h[(k >> 10) & 0x7FF], 1u);
+    } else if ((k >> 10) == p12) {
+      atomicAdd(&h[k & 0x3FF], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// sel: [0..2] digits, [3] ranks still to take, [4] threshold key, [5] k.
+__global__ void k_topk_pick(uint32_t *hist, uint32_t *sel, int pass, uint32_t k) {
+  __shared__ uint32_t part[256];
+  const int t = threadIdx.x;
+  const uint32_t need = pass == 0 ? k : sel[3];
+  uint32_t s = 0;
+  for (int i = 0; i < 8; ++i) s += hist[t * 8 + i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    int bin = 2047;
+    uint32_t below = 0;
+    bool found = false;
+    for (int w = 0; w < 256 && !found; ++w) {
+      if (run + part[w] >= need) {
+        uint32_t r2 = run;
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t hv = hist[w * 8 + i];
+          if (r2 + hv >= need) {
+            bin = w * 8 + i;
+            below = r2;
+            found = true;
+            break;
+          }
+          r2 += hv;
+        }
+      }
+      run += part[w];
+    }
+    if (!found) below = run;  // fewer keys than k: take them all
+    sel[pass] = (uint32_t)bin;
+    sel[3] = need - below;
+    if (pass == 0) sel[5] = k;
+    if (pass == 2) sel[4] = (sel[0] << 21) | (sel[1] << 10) | sel[2];
+  }
+  __syncthreads();
+  for (int i = t; i < 2048; i += blockDim.x) hist[i] = 0;
+}
+
+__device__ __forceinline__ void block_counts(uint32_t n, uint32_t &lo, uint32_t &hi) {
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  lo = blockIdx.x * per;
+  hi = lo + per < n ? lo + per : n;
+  if (lo > n) lo = n;
+}
+
+__global__ void k_topk_count(const uint32_t *keys, uint32_t n, const uint32_t *sel, uint32_t *blk) {
+  __shared__ uint32_t c_lt, c_eq;
+  if (threadIdx.x == 0) c_lt = c_eq = 0;
+  __syncthreads();
+  uint32_t lo, hi;
+  block_counts(n, lo, hi);
+  const uint32_t T = sel[4];
+  uint32_t lt = 0, eq = 0;
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const uint32_t k = keys[i];
+    lt += k < T;
+    eq += k == T;
+  }
+  atomicAdd(&c_lt, lt);
+  atomicAdd(&c_eq, eq);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x] = c_lt;
+    blk[gridDim.x + blockIdx.x] = c_eq;
+  }
+}
+
+// Exclusive scans of the per-block counts (nblk <= 1024, one block).
+__global__ void k_topk_scan(uint32_t *blk, uint32_t nblk) {
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (uint32_t i = 0; i < nblk; ++i) {
+      const uint32_t x = blk[i], y = blk[nblk + i];
+      blk[i] = a;
+      blk[nblk + i] = b;
+      a += x;
+      b += y;
+    }
+  }
+}
+
+__global__ void k_topk_write(const uint32_t *keys, uint32_t n, const uint32_t *sel, const uint32_t *blk,
+                             uint32_t *out) {
+  __shared__ uint32_t w_lt[8], w_eq[8];
+  uint32_t lo, hi;
+  block_counts(n, lo, hi);
+  const uint32_t T = sel[4], need_eq = sel[3], k = sel[5];
+  const uint32_t n_lt = k - need_eq;
+  uint32_t off_lt = blk[blockIdx.x], off_eq = blk[gridDim.x + blockIdx.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (uint32_t base = lo; base < hi; base += blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t key = i < hi ? keys[i] : 0xFFFFFFFFu;
+    const bool is_lt = i < hi && key < T, is_eq = i < hi && key == T;
+    const uint64_t bl = __ballot(is_lt), be = __ballot(is_eq);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (lane == 0) {
+      w_lt[wave] = (uint32_t)__popcll(bl);
+      w_eq[wave] = (uint32_t)__popcll(be);
+    }
+    __syncthreads();
+    uint32_t pl = 0, pe = 0, tl = 0, te = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wave) {
+        pl += w_lt[w];
+        pe += w_eq[w];
+      }
+      tl += w_lt[w];
+      te += w_eq[w];
+    }
+    if (is_lt) out[off_lt + pl + (uint32_t)__popcll(bl & below)] = i;
+    if (is_eq) {
+      const uint32_t r = off_eq + pe + (uint32_t)__popcll(be & below);
+      if (r < need_eq) out[n_lt + r] = i;
+    }
+    off_lt += tl;
+    off_eq += te;
+    __syncthreads();
+  }
+}
+
+// Scores of the screened proposals as floats (+inf: discarded).
+__global__ void k_scr_export(const uint32_t *keys, uint32_t n, float *out) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    out[i] = k == 0xFFFFFFFFu ? __builtin_inff() : key_score(k);
+  }
+}
+
+// Mean relative error of the predicted path on the exactly evaluated
+// shortlist, and the fallback decision (no ranked candidate, or the error
+// above the threshold).  One block.
+__global__ void k_scr_check(InstParams P, SurDev S, ScreenDev T, uint32_t k, float err_thr) {
+  __shared__ float s_err[256];
+  __shared__ uint32_t s_cnt[256];
+  float e = 0.f;
+  uint32_t cnt = 0;
+  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
+    const float cost = T.short_cost[j];
+    const uint32_t key = T.keys[T.short_idx[j]];
+    if (!__builtin_isfinite(cost) || key == 0xFFFFFFFFu || cost <= 0.f) continue;
+    const float pred_km = key_score(key) / S.inv_c0 * 1e-3f;
+    e += fabsf(pred_km - cost) / cost;
+    ++cnt;
+  }
+  s_err[threadIdx.x] = e;
+  s_cnt[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float te = 0.f;
+    uint32_t tc = 0;
+    for (int i = 0; i < (int)blockDim.x; ++i) {
+      te += s_err[i];
+      tc += s_cnt[i];
+    }
+    const float mean = tc ? te / (float)tc : __builtin_inff();
+    const uint32_t fb = (*P.best_key == kInfKey || mean > err_thr) ? 1u : 0u;
+    *T.flag = fb;
+    T.stats[0] = mean;
+    T.stats[1] += (float)fb;
+    T.stats[2] += 1.f;
+    T.stats[3] = (float)tc;
+  }
+}
+
 }  // namespace
 
 // Sizes of the bf16 operand copies (elements).
@@ -586,6 +1149,50 @@ hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float 
 }
 
 size_t sur_head_lds(const InstParams &P) { return (size_t)4 * P.NB * kSurA * 4; }
+
+// Screen n_prop proposals against the base: base forward and tables, then
+// chunks of descriptors + changed rows -> MLP rows -> scores, then the k
+// best-predicted proposal indices into T.short_idx.
+hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
+                         uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
+                         uint32_t chunk, int n_cu, hipStream_t s) {
+  hipError_t e = launch_sur_forward(P, S, nullptr, 1, 1, false, n_cu, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scr_tables, dim3(1), dim3(64), 0, s, P, S, T);
+  const size_t lds_img = (size_t)round4(P.lay.total_words) * 4;
+  const size_t lds_fwd = (size_t)(128 * kLd1 + 128 * kLd2 + 64 * kLd2) * 2 + 256 * 4 + 4 * 16 * kLd2 * 2;
+  for (uint32_t i0 = 0; i0 < n_prop; i0 += chunk) {
+    const uint32_t cnt = std::min(chunk, n_prop - i0);
+    const uint32_t gb = std::min<uint32_t>((cnt + 255) / 256, (uint32_t)n_cu * 4);
+    hipLaunchKernelGGL(k_scr_rows, dim3(gb), dim3(256), lds_img, s, P, S, T, seed, inst_index, i0, cnt);
+    const uint32_t rows = 3 * cnt, tiles = (rows + 15) / 16;
+    const uint32_t gf = std::min<uint32_t>((tiles + 3) / 4, (uint32_t)n_cu * 2);
+    hipLaunchKernelGGL(k_sur_fwd, dim3(gf), dim3(256), lds_fwd, s, S, S.phi, rows, S.P, nullptr, nullptr);
+    hipLaunchKernelGGL(k_scr_score, dim3(gb), dim3(256), 0, s, P, S, T, i0, cnt, mk_margin);
+  }
+  hipLaunchKernelGGL(k_sur_zero, dim3(8), dim3(256), 0, s, reinterpret_cast<float *>(T.hist), 2048u);
+  hipLaunchKernelGGL(k_sur_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(T.sel), 8u);
+  for (int pass = 0; pass < 3; ++pass) {
+    hipLaunchKernelGGL(k_topk_hist, dim3(1024), dim3(256), 0, s, T.keys, n_prop, pass, T.sel, T.hist);
+    hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(256), 0, s, T.hist, T.sel, pass, k);
+  }
+  hipLaunchKernelGGL(k_topk_count, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk);
+  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(64), 0, s, T.blk, 1024u);
+  hipLaunchKernelGGL(k_topk_write, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk, T.short_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s) {
+  const uint32_t gb = std::min<uint32_t>((n + 255) / 256, 1024u);
+  hipLaunchKernelGGL(k_scr_export, dim3(gb), dim3(256), 0, s, T.keys, n, score);
+  return hipGetLastError();
+}
+
+hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,
+                            float err_thr, hipStream_t s) {
+  hipLaunchKernelGGL(k_scr_check, dim3(1), dim3(256), 0, s, P, S, T, k, err_thr);
+  return hipGetLastError();
+}
 
 hipError_t sur_setup_attributes() {
   const int fwd = (128 * kLd1 + 128 * kLd2 + 64 * kLd2) * 2 + 256 * 4 + 4 * 16 * kLd2 * 2;

@@ -1,0 +1,169 @@
+"""The learned screen's incremental inference and the screened iteration on
+the GPU.
+
+* Scores: the screen recomputes only the rows, BP means and tours a proposal
+  changes; its predicted path must equal the library's full forward pass
+  (bl_sur_predict, itself checked against the float64 reference) on the same
+  proposals up to float32 summation order, and its discards must be exactly
+  the proposals that break eq. (2) (an integer decision) or whose predicted
+  makespan is above the gate.
+* Shortlist: exactly the n_shortlist smallest scores, lowest index first
+  among equal scores (index work: bit-exact).
+* Screened iteration: given the shortlist, the iteration is the oracle's
+  iteration with every other proposal left out (keys, trace, solutions
+  bit-exact); with the fallback forced it is the plain iteration.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import model as M
+from oracle import moves as MV
+from oracle import search as S
+
+from paper_1909_10286_amd import bl
+
+from .gpu_common import from_csr, to_csr
+from .sur_common import setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _screen(ctx, sur, seed, eps, n, k, margin):
+    d_short = torch.empty(k, dtype=torch.int32, device="cuda")
+    d_score = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.sur_screen(sur, seed, eps, n, k, d_short, d_score, mk_margin=margin)
+    torch.cuda.synchronize()
+    return d_short.cpu().numpy().view(np.uint32).astype(np.int64), d_score.cpu().numpy()
+
+
+def _predict(ctx, iid, sur, seed, n):
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(iid, seed, 0, 0, 0, n, d_mv)
+    d_out = torch.empty(2 * n, dtype=torch.float32, device="cuda")
+    ctx.sur_predict(sur, d_mv, n, d_out)
+    torch.cuda.synchronize()
+    return d_mv.cpu().numpy().view(np.uint64), d_out.cpu().numpy().reshape(-1, 2).astype(np.float64)
+
+
+def _expected_shortlist(score, k):
+    return np.sort(np.argsort(score, kind="stable")[:k])
+
+
+@pytest.mark.parametrize("name,n,k", [("tiny12", 5000, 128), ("mid100", 8192, 512),
+                                      ("clust500", 4096, 300)])
+def test_screen_scores_match_full_forward(ctx, name, n, k):
+    _say("screen scores", name, n, k)
+    inst, st, iid, sur, p, sc = setup(ctx, name)
+    ctx.search_start(iid, 4)
+    seed, eps = 21, 1 << 32          # eps threshold 2^32: the base is x*
+    short, score = _screen(ctx, sur, seed, eps, n, k, margin=1e9)
+    words, pred = _predict(ctx, iid, sur, seed, n)
+    base = st.x_best
+    feas = np.array([M.is_feasible(inst, MV.apply_move(base, MV.decode(int(w)))) for w in words])
+    # With an unreachable makespan gate, exactly the eq. (2) breakers are discarded.
+    assert np.array_equal(np.isfinite(score), feas), np.nonzero(np.isfinite(score) != feas)[0][:10]
+    tol = 1e-4 * np.abs(pred[:, 0]).max() + 1e-6
+    err = np.abs(score[feas] - pred[feas, 0])
+    assert err.max() <= tol, (err.max(), tol)
+    assert np.array_equal(short, _expected_shortlist(score, k))
+
+    # The makespan gate: predicted makespan above t_best / t0 + margin drops out.
+    margin = float(np.median(pred[feas, 1])) - 1.0   # t0 = t_best: the gate sits at the median
+    short2, score2 = _screen(ctx, sur, seed, eps, n, k, margin=margin)
+    gate = 1.0 + margin
+    mtol = 1e-4 * np.abs(pred[:, 1]).max() + 1e-6
+    clear_in = feas & (pred[:, 1] < gate - mtol)
+    clear_out = ~feas | (pred[:, 1] > gate + mtol)
+    assert np.isfinite(score2[clear_in]).all()
+    assert not np.isfinite(score2[clear_out]).any()
+    assert np.array_equal(short2, _expected_shortlist(score2, k))
+
+
+def _oracle_subset_step(inst, st, seed, n, eps, subset, force_all=False):
+    def keys(job, nn):
+        out = [M.INF_KEY] * nn
+        for i in (range(nn) if force_all else subset):
+            out[int(i)] = S.candidate(job, int(i))[0]
+        return out
+    return S.step(inst, st, seed, n, eps, map_fn=keys)
+
+
+def _compare(ctx, iid, st, row):
+    g = ctx.search_trace(iid)[-1]
+    o = st.trace[-1]
+    mk = bl.INF_MAKESPAN if o.makespan_s == M.INF else o.makespan_s
+    assert (g["it"], g["best_key"], g["cost_m"], g["makespan_s"], g["indicator"], bool(g["use_best"])) == \
+        (o.it, o.best_key, o.cost_m, mk, o.indicator, o.use_best), (row, g, o)
+    assert from_csr(ctx.solution_download(iid, bl.SLOT_OLD)) == st.x_old
+    assert from_csr(ctx.solution_download(iid, bl.SLOT_BEST)) == st.x_best
+
+
+@pytest.mark.parametrize("name,n,k,iters", [("tiny12", 1024, 64, 6), ("mid100", 4096, 96, 3)])
+def test_screened_iteration_matches_oracle_on_shortlist(ctx, name, n, k, iters):
+    """Each iteration: the shortlist the screen picks, then the oracle's
+    iteration restricted to it (or the plain iteration when the shortlist has
+    no candidate that passes the exact gate)."""
+    _say("screened iteration", name, n, k, iters)
+    inst, st, iid, sur, p, sc = setup(ctx, name)
+    ctx.search_start(iid, iters)
+    seed, eps = 5, S.eps_threshold(0.5)
+    fallbacks = 0
+    for it in range(iters):
+        short, score = _screen(ctx, sur, seed, eps, n, k, margin=0.5)
+        ctx.sur_search_step(sur, seed, eps, n, k, n, mk_margin=0.5, err_threshold=math.inf)
+        torch.cuda.synchronize()
+        trial = _oracle_subset_step(inst, st, seed, n, eps, short)
+        if trial.trace[-1].best_key == M.INF_KEY:
+            trial = _oracle_subset_step(inst, st, seed, n, eps, short, force_all=True)
+            fallbacks += 1
+        st = trial
+        _compare(ctx, iid, st, it)
+    stats = ctx.sur_stats(sur)
+    assert stats["iterations"] == iters and stats["fallbacks"] == fallbacks
+
+
+@pytest.mark.parametrize("name,n,iters", [("tiny12", 2048, 8), ("mid100", 4096, 3)])
+def test_forced_fallback_is_the_plain_search(ctx, name, n, iters):
+    """err_threshold below any error forces the fallback every iteration;
+    with n_fallback = n_proposals the argmin covers every proposal, so the
+    trajectory is the plain search's, bit for bit."""
+    _say("forced fallback", name, n, iters)
+    inst, st, iid, sur, p, sc = setup(ctx, name)
+    seed, eps = 11, S.eps_threshold(0.5)
+    ctx.search_start(iid, iters)
+    for _ in range(iters):
+        ctx.search_step(iid, seed, eps, n)
+    torch.cuda.synchronize()
+    plain = ctx.search_trace(iid)
+    ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(st.x_best))
+    ctx.search_start(iid, iters)
+    for _ in range(iters):
+        ctx.sur_search_step(sur, seed, eps, n, 32, n, mk_margin=0.0, err_threshold=-1.0)
+    torch.cuda.synchronize()
+    assert ctx.search_trace(iid) == plain
+    stats = ctx.sur_stats(sur)
+    assert stats["iterations"] == iters and stats["fallbacks"] == iters
+
+
+def test_screen_rejects_bad_sizes(ctx):
+    inst, st, iid, sur, p, sc = setup(ctx, "tiny12")
+    d = torch.empty(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(bl.BlError):
+        ctx.sur_screen(sur, 0, 0, 64, 64, d)          # search not started
+    ctx.search_start(iid, 0)
+    with pytest.raises(bl.BlError):
+        ctx.sur_screen(sur, 0, 0, 32, 64, d)          # shortlist longer than the proposals
+    with pytest.raises(bl.BlError):
+        ctx.sur_screen(sur, 0, 0, 0, 1, d)
+    with pytest.raises(bl.BlError):
+        ctx.sur_search_step(sur, 0, 0, (1 << 24) + 1, 1, 0)

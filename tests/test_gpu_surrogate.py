@@ -6,14 +6,12 @@ import sys
 import numpy as np
 import pytest
 
-from oracle import init as OI
 from oracle import model as M
 from oracle import moves as MV
-from oracle import search as S
 from oracle import surrogate as SG
-from paper_1909_10286_amd import bl, inputs
+from paper_1909_10286_amd import bl
 
-from .gpu_common import to_csr
+from .sur_common import draw_moves as _moves, flat as _flat, setup, unflat as _unflat
 
 pytestmark = pytest.mark.gpu
 
@@ -25,46 +23,9 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _flat(p):
-    return np.concatenate([p[k].reshape(-1) for k, _ in bl.SUR_SHAPES]).astype(np.float32)
-
-
-def _unflat(w):
-    out, k = {}, 0
-    for name, shape in bl.SUR_SHAPES:
-        n = int(np.prod(shape))
-        out[name] = np.asarray(w[k:k + n], dtype=np.float64).reshape(shape)
-        k += n
-    return out
-
-
 def _setup(ctx, name, wseed=3):
-    inst = inputs.make_instance(name, 0, accept=OI.init_feasible)
-    st = S.start(inst, OI.init_solution(inst))
-    base = st.x_best
-    iid = ctx.instance_upload(inst)
-    ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(base))
-    p = SG.init_params(inputs.surrogate_init_words(wseed))
-    rng = np.random.default_rng(wseed)
-    for k in ("b1", "b2", "b3", "b4"):
-        p[k] = rng.normal(0, 0.1, p[k].shape)
-    # Round the reference weights to float32, the precision the library keeps.
-    p = _unflat(_flat(p))
-    sur = ctx.sur_create(iid, _flat(p), float(st.cost_best), float(st.t_best), max_examples=512)
-    sc = SG.scales(inst, st.cost_best, st.t_best)
-    return inst, base, iid, sur, p, sc
-
-
-def _moves(inst, base, n, seed=7, feasible_only=True):
-    out = []
-    i = 0
-    while len(out) < n:
-        mv = MV.draw_move(inst, base, seed, 0, i)
-        i += 1
-        if feasible_only and not M.is_feasible(inst, MV.apply_move(base, mv)):
-            continue
-        out.append(mv)
-    return out
+    inst, st, iid, sur, p, sc = setup(ctx, name, wseed)
+    return inst, st.x_best, iid, sur, p, sc
 
 
 @pytest.mark.parametrize("name", ["tiny12", "mid100", "clust500"])
