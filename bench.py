@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (scale for the HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,6 +157,15 @@ def main():
 
     from paper_1909_10286_amd import bl, inputs
 
+    if a.copy_calibration:
+        src = torch.ones((256 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 256 << 20, "copies": 3}), flush=True)
+        return
     if a.workload == "batch256":
         return bench_batch(a)
     wl = inputs.WORKLOADS[a.workload]

@@ -50,6 +50,10 @@ typedef int32_t bl_status;
 #define BL_NO_EMBEDDED_MIN 2u /* Case 2 of sec. 3.2: units never move between tours   */
 #define BL_GATE_OFF 4u        /* no makespan gate (Case 2)                             */
 #define BL_GATE_STRICT 8u     /* discard when makespan >= T* (default: when > T*)      */
+#define BL_FULL_WALK 16u      /* evaluate every candidate by walking all its routes,
+                                 instead of from the base's per-tour and per-BP
+                                 aggregates and the legs the move changes (same
+                                 results; the walk is the plain reading of sec. 2.2) */
 
 /* Per-candidate flags written by bl_evaluate_batch. */
 #define BL_CAND_INFEASIBLE 1u   /* eq. (2) violated; cost and makespan not evaluated */
@@ -92,7 +96,7 @@ typedef struct {
   const int32_t *xy_m;          /* [2 * V] or NULL: coordinates (learned screen features) */
   const uint16_t *init_hus_per_tour; /* [n_tours] or NULL: initial HU block sizes */
   const uint16_t *init_sus_per_tour; /* [n_tours] or NULL: initial SU block sizes */
-  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* */
+  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* | BL_FULL_WALK */
   uint32_t cap_hu, cap_su;      /* rebalancing round caps; 0 = units + tours */
 } bl_instance;
 

@@ -18,7 +18,7 @@ constexpr int64_t kInfT = INT64_MAX;
 constexpr int64_t kNegInfT = INT64_MIN;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8 };
+enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8, kFullWalk = 16 };
 enum : uint32_t {
   kCandInfeasible = 1, kCandGated = 2, kCandCapHu = 4, kCandCapSu = 8, kCandInvalid = 16,
   kCandInfMakespan = 32
@@ -50,6 +50,20 @@ struct ImageLayout {
   uint32_t tour_bp;   // u16 [NB]: BPs in tour order
   uint32_t hu_mask;   // u64 per tour: HU ranks held
   uint32_t su_mask;   // 2 x u64 per tour: SU ranks held
+  // base aggregates, from which a candidate's tours follow in O(1)
+  uint32_t t_len;     // u32 per tour: route length L(g), m
+  uint32_t t_area;    // u32 per tour: area
+  uint32_t t_sh;      // u64 per tour: shuttle distance
+  uint32_t t_msum;    // u32 per tour: sum over its BPs with fields of floor(sum D[f][b] / |F_b|)
+  uint32_t t_mcnt;    // u32 per tour: number of its BPs with fields
+  uint32_t t_start;   // u16 per tour: first position of its fields
+  uint32_t t_end;     // u16 per tour: one past its last position
+  uint32_t b_sd;      // u32 per BP: sum of D[f][b] over its fields
+  uint32_t b_sup;     // u32 per BP: supply, kg
+  uint32_t b_area;    // u32 per BP: area
+  uint32_t b_sh;      // u64 per BP: shuttle distance
+  uint32_t b_int;     // u32 per BP: legs between its consecutive fields
+  uint32_t n_viol;    // u32: BPs whose supply is below their demand
   uint32_t static_words, total_words;
 };
 
@@ -105,6 +119,7 @@ struct BatchParams {
   const uint32_t *order;     // [K] schedule position -> member
   const uint32_t *tile;      // [K] candidates per item, by member
   uint32_t *queue;           // [1] next item to pop
+  uint32_t walk;             // some member asks for the full walk (host side)
 };
 
 // ---- learned screen (set encoder) ----
@@ -162,8 +177,7 @@ struct ScreenDev {
   float *U;                  // [NT][64] b3 + tour features through W3 rows 128..135
   float *ub6;                // [NT] base return-leg feature
   float *yb;                 // [NT][2] base head outputs
-  int32_t *nbg, *nfg, *tstart, *tend;  // [NT] BP / field counts, position range
-  uint32_t *bsupply;         // [NB] supply of the base's fields per BP, kg
+  int32_t *nbg, *nfg;        // [NT] BP / field counts
   float *scal;               // [4]: predicted base path, top-3 base completion outputs
   int32_t *top_g;            // [3] tours of those top-3 outputs
   ScreenDesc *desc;          // [chunk]
@@ -198,7 +212,7 @@ hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStr
 size_t eval_lds_bytes(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);
-int batch_occupancy(size_t lds);
+int batch_occupancy(size_t lds, bool walk);
 hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s);
 hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s);
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s);

@@ -46,6 +46,9 @@ struct View {
   const uint4 *prec;   // per position: {leg in, D[field][BP], area, supply}
   const uint32_t *w_q;  // per position: shuttle distance
   const uint64_t *hu_mask, *su_mask;
+  const uint32_t *t_len, *t_area, *t_msum, *t_mcnt, *b_sd, *b_sup, *b_area, *b_int, *n_viol;
+  const uint64_t *t_sh, *b_sh;
+  const uint16_t *t_start, *t_end;
   const uint32_t *D;
 };
 
@@ -76,6 +79,19 @@ __device__ __forceinline__ View make_view(const uint32_t *img, const ImageLayout
   v.tour_bp = (const uint16_t *)(img + L.tour_bp);
   v.hu_mask = (const uint64_t *)(img + L.hu_mask);
   v.su_mask = (const uint64_t *)(img + L.su_mask);
+  v.t_len = img + L.t_len;
+  v.t_area = img + L.t_area;
+  v.t_msum = img + L.t_msum;
+  v.t_mcnt = img + L.t_mcnt;
+  v.b_sd = img + L.b_sd;
+  v.b_sup = img + L.b_sup;
+  v.b_area = img + L.b_area;
+  v.b_int = img + L.b_int;
+  v.n_viol = img + L.n_viol;
+  v.t_sh = (const uint64_t *)(img + L.t_sh);
+  v.b_sh = (const uint64_t *)(img + L.b_sh);
+  v.t_start = (const uint16_t *)(img + L.t_start);
+  v.t_end = (const uint16_t *)(img + L.t_end);
   v.D = D;
   return v;
 }
@@ -225,6 +241,185 @@ __device__ __forceinline__ Pieces bp_pieces(const View &V, const Move &m, int b)
   return p;
 }
 
+// ------------------------------------------------ delta evaluation ----
+// Route neighbours of the moved vertex: the field, or the BP's run of fields
+// [q0, q1) in base positions.  pold/nold surround it in the base; pnew/nnew
+// surround its insertion point in the route after its removal.  -1 is HQ.
+// An empty moved BP leaves every route unchanged (first = -1).
+struct Nbrs {
+  int q0, q1, first, last, pold, nold, pnew, nnew;
+};
+
+__device__ __forceinline__ Nbrs move_nbrs(const View &V, const Move &m) {
+  Nbrs n;
+  if (m.kind == 0) {
+    const int f = m.v, bs = m.src, bd = m.dst, r = m.r, s = m.slot;
+    const int Ts = V.bp_tour[bs], Td = V.bp_tour[bd];
+    const int qf = V.pos[f];
+    n.q0 = qf;
+    n.q1 = qf + 1;
+    n.first = n.last = f;
+    n.pold = qf > (int)V.t_start[Ts] ? V.seq[qf - 1] : -1;
+    n.nold = qf + 1 < (int)V.t_end[Ts] ? V.seq[qf + 1] : -1;
+    const int st = V.bp_start[bd], len = V.bp_len[bd];
+    const int room = len - (bd == bs ? 1 : 0);
+    if (s > 0) {
+      int k = s - 1;
+      if (bd == bs && k >= r) ++k;
+      n.pnew = V.seq[st + k];
+    } else {
+      int pp = st - 1;
+      if (pp == qf) --pp;
+      n.pnew = pp >= (int)V.t_start[Td] ? V.seq[pp] : -1;
+    }
+    if (s < room) {
+      int k = s;
+      if (bd == bs && k >= r) ++k;
+      n.nnew = V.seq[st + k];
+    } else {
+      int pp = st + len;
+      if (pp == qf) ++pp;
+      n.nnew = pp < (int)V.t_end[Td] ? V.seq[pp] : -1;
+    }
+  } else {
+    const int b = m.v, s = m.slot, r = m.r, Ts = m.src, Td = m.dst;
+    const int q0 = V.bp_start[b], q1 = q0 + V.bp_len[b];
+    n.q0 = q0;
+    n.q1 = q1;
+    n.first = n.last = n.pold = n.nold = n.pnew = n.nnew = -1;
+    if (q1 == q0) return n;
+    n.first = V.seq[q0];
+    n.last = V.seq[q1 - 1];
+    n.pold = q0 > (int)V.t_start[Ts] ? V.seq[q0 - 1] : -1;
+    n.nold = q1 < (int)V.t_end[Ts] ? V.seq[q1] : -1;
+    const int room = tour_len(V, Td) - (Td == Ts ? 1 : 0);
+    int ip;
+    if (s < room) {
+      int j = s;
+      if (Td == Ts && j >= r) ++j;
+      ip = V.bp_start[V.tour_bp[V.tour_off[Td] + j]];
+    } else {
+      ip = V.t_end[Td];
+    }
+    int pp = ip - 1;
+    if (pp >= q0 && pp < q1) pp = q0 - 1;
+    n.pnew = pp >= (int)V.t_start[Td] ? V.seq[pp] : -1;
+    pp = ip;
+    if (pp >= q0 && pp < q1) pp = q1;
+    n.nnew = pp < (int)V.t_end[Td] ? V.seq[pp] : -1;
+  }
+  return n;
+}
+
+// Road distance between two fields, HQ standing for -1 on either side.
+__device__ __forceinline__ uint32_t route_leg(const View &V, const InstParams &P, int a, int b) {
+  if (a < 0) return b < 0 ? 0u : V.dhq[b];
+  if (b < 0) return V.dhq[a];
+  const size_t nb1 = 1 + (size_t)P.NB;
+  return V.D[(nb1 + (size_t)a) * (size_t)P.V + nb1 + (size_t)b];
+}
+
+__device__ __forceinline__ uint32_t bp_mean(uint32_t sd, uint32_t cnt) { return cnt ? sd / cnt : 0u; }
+
+// Tour t of the candidate from the base's aggregates: only the source and
+// destination tours change, by the legs the move cuts and creates and by the
+// moved fields' sums.  Integer results equal the full walk's.
+__device__ __forceinline__ void tour_delta(const View &V, const InstParams &P, const Move &m,
+                                           const Nbrs &nb, int t, uint32_t &L, uint32_t &A,
+                                           uint64_t &sh, uint32_t &msum, uint32_t &mcnt, bool &act) {
+  L = V.t_len[t];
+  A = V.t_area[t];
+  sh = V.t_sh[t];
+  msum = V.t_msum[t];
+  mcnt = V.t_mcnt[t];
+  int nf = (int)V.t_end[t] - (int)V.t_start[t];
+  const int Ts = m.kind == 0 ? (int)V.bp_tour[m.src] : m.src;
+  const int Td = m.kind == 0 ? (int)V.bp_tour[m.dst] : m.dst;
+  if ((t == Ts || t == Td) && nb.first >= 0) {
+    int64_t dL = 0;
+    // Legs into and out of the moved run in the base, and the legs created.
+    const bool same_gap = nb.pnew == nb.pold && nb.nnew == nb.nold;
+    uint32_t bridge = 0;
+    if (t == Ts || same_gap) bridge = route_leg(V, P, nb.pold, nb.nold);
+    // A moved BP takes its internal legs along to the other tour.
+    const int64_t inner = (m.kind == 1 && Ts != Td) ? (int64_t)V.b_int[m.v] : 0;
+    if (t == Ts) {
+      const uint32_t lin = nb.pold < 0 ? V.dhq[nb.first] : V.prec[nb.q0].x;
+      const uint32_t lout = nb.nold < 0 ? V.dhq[nb.last] : V.prec[nb.q1].x;
+      dL += (int64_t)bridge - (int64_t)lin - (int64_t)lout - inner;
+    }
+    if (t == Td) {
+      uint32_t gap;
+      if (same_gap) {
+        gap = bridge;
+      } else if (nb.pnew < 0 || nb.nnew < 0) {
+        gap = route_leg(V, P, nb.pnew, nb.nnew);
+      } else {
+        const int qn = V.pos[nb.nnew];
+        gap = qn > 0 && V.seq[qn - 1] == nb.pnew ? V.prec[qn].x : route_leg(V, P, nb.pnew, nb.nnew);
+      }
+      dL += (int64_t)route_leg(V, P, nb.pnew, nb.first) + (int64_t)route_leg(V, P, nb.last, nb.nnew) -
+            (int64_t)gap + inner;
+    }
+    L = (uint32_t)((int64_t)L + dL);
+    if (m.kind == 0) {
+      const int f = m.v, bs = m.src, bd = m.dst;
+      if (bs != bd) {
+        const uint32_t dfs = V.prec[nb.q0].y;
+        const size_t nb1 = 1 + (size_t)P.NB;
+        const uint32_t dfd = V.D[(nb1 + (size_t)f) * (size_t)P.V + 1 + (size_t)bd];
+        if (t == Ts) {
+          const uint32_t cs = V.bp_len[bs];
+          msum = msum - bp_mean(V.b_sd[bs], cs) + bp_mean(V.b_sd[bs] - dfs, cs - 1);
+          mcnt -= cs == 1 ? 1u : 0u;
+          A -= V.area[f];
+          sh -= V.w_q[nb.q0];
+          nf -= 1;
+        }
+        if (t == Td) {
+          const uint32_t cd = V.bp_len[bd];
+          msum = msum - bp_mean(V.b_sd[bd], cd) + bp_mean(V.b_sd[bd] + dfd, cd + 1);
+          mcnt += cd == 0 ? 1u : 0u;
+          A += V.area[f];
+          sh += 2ull * (uint64_t)V.nsh[f] * (uint64_t)dfd;
+          nf += 1;
+        }
+      }
+    } else if (Ts != Td) {
+      const int b = m.v;
+      const uint32_t mb = bp_mean(V.b_sd[b], V.bp_len[b]);
+      const int len = V.bp_len[b];
+      if (t == Ts) {
+        msum -= mb;
+        mcnt -= 1;
+        A -= V.b_area[b];
+        sh -= V.b_sh[b];
+        nf -= len;
+      } else {
+        msum += mb;
+        mcnt += 1;
+        A += V.b_area[b];
+        sh += V.b_sh[b];
+        nf += len;
+      }
+    }
+  }
+  act = nf > 0;
+}
+
+// eq. (2) for the candidate: the base's violations corrected at the two BPs
+// a field move changes.  Uniform over the segment.
+__device__ __forceinline__ bool delta_feasible(const View &V, const Move &m) {
+  int viol = (int)V.n_viol[0];
+  if (m.kind == 0 && m.src != m.dst) {
+    const int bs = m.src, bd = m.dst;
+    const uint32_t sf = V.supply[m.v], ss = V.b_sup[bs], sd = V.b_sup[bd];
+    const uint32_t ds = V.demand[bs], dd = V.demand[bd];
+    viol += (int)(ss - sf < ds) - (int)(ss < ds) + (int)(sd + sf < dd) - (int)(sd < dd);
+  }
+  return viol == 0;
+}
+
 // ------------------------------------------------- segment reductions --
 // (value, tour) packed so that one unsigned max / min is the arg-max /
 // arg-min with the lowest tour winning ties.  Values live in (-2^57, 2^57).
@@ -338,6 +533,7 @@ struct EvalOut {
 
 // Evaluate one candidate on the S lanes of a segment (lane t owns tour t).
 // `gate`: 0 = off, 1 = discard when makespan > t_star, 2 = when >= t_star.
+template <bool WALK>
 __device__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move &m, int t,
                                   int S, int seg_base, uint64_t seg_mask) {
   EvalOut o;
@@ -350,7 +546,11 @@ __device__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move
   uint32_t L = 0, A = 0, sum_mean = 0, n_mean = 0;
   uint64_t shuttle = 0;
   bool feas = true, act = false;
-  if (lane_tour) {
+  if constexpr (!WALK) {
+    const Nbrs nb = move_nbrs(V, m);
+    if (lane_tour) tour_delta(V, P, m, nb, t, L, A, shuttle, sum_mean, n_mean, act);
+    feas = delta_feasible(V, m);
+  } else if (lane_tour) {
     const int nbt = cand_tour_len(V, m, t);
     const size_t Vn = (size_t)P.V;
     const int nb1 = 1 + P.NB;
@@ -409,7 +609,10 @@ __device__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move
       act = true;
     }
   }
-  o.feasible = seg_ballot(!feas, seg_base, seg_mask) == 0;
+  if constexpr (WALK)
+    o.feasible = seg_ballot(!feas, seg_base, seg_mask) == 0;
+  else
+    o.feasible = feas;
   uint64_t hm = lane_tour ? V.hu_mask[t] : 0ull;
   M128 sm = lane_tour ? M128{V.su_mask[2 * t], V.su_mask[2 * t + 1]} : M128{0ull, 0ull};
   if (!o.feasible) {
@@ -584,6 +787,7 @@ struct CandResult {
 };
 
 // Full evaluation of move word w as candidate c (all segment lanes call it).
+template <bool WALK>
 __device__ __forceinline__ CandResult eval_one(const View &V, const InstParams &P, uint64_t w,
                                                uint32_t c, int t, int S, int seg_base,
                                                uint64_t seg_mask, int64_t t_star) {
@@ -593,7 +797,7 @@ __device__ __forceinline__ CandResult eval_one(const View &V, const InstParams &
     r.flags = kCandInvalid;
     return r;
   }
-  const EvalOut o = eval_candidate(V, P, m, t, S, seg_base, seg_mask);
+  const EvalOut o = eval_candidate<WALK>(V, P, m, t, S, seg_base, seg_mask);
   r.flags = o.flags;
   if (o.feasible) {
     r.cost_km = (float)((double)o.cost / 1000.0);

@@ -31,7 +31,7 @@ namespace {
 // drawn for indices 0..n-1, argmin into the instance's slot) and gather
 // (moves drawn for the indices listed in `gather`, per-entry outputs and the
 // argmin).  `run_flag` (nullable): the launch does nothing while it is 0.
-template <bool DLDS, int MODE>
+template <bool DLDS, int MODE, bool WALK>
 __global__ __launch_bounds__(256) void k_eval(InstParams P, const uint64_t *__restrict__ moves,
                                               uint32_t n, int64_t t_star_arg, uint64_t seed,
                                               uint32_t inst_index, uint64_t *__restrict__ out_key,
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_eval(InstParams P, const uint64_t *__re
   for (uint32_t c = gseg; c < n; c += nseg) {
     const uint32_t ci = MODE == kModeGather ? gather[c] : c;
     const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
-    const CandResult r = eval_one(V, P, w, ci, t, S, seg_base, seg_mask, t_star);
+    const CandResult r = eval_one<WALK>(V, P, w, ci, t, S, seg_base, seg_mask, t_star);
     if (MODE != kModeSearch && t == 0) {
       if (out_key) out_key[c] = r.key;
       if (out_cost) out_cost[c] = r.cost_km;
@@ -117,6 +117,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   uint4 *prec = (uint4 *)(img + L.prec);
   uint32_t *w_q = img + L.w_q;
   const uint32_t *f_area = img + L.area, *f_supply = img + L.supply, *f_nsh = img + L.nsh;
+  const uint32_t *f_dhq = img + L.dhq, *demand = img + L.demand;
   uint64_t *hu_mask = (uint64_t *)(img + L.hu_mask), *su_mask = (uint64_t *)(img + L.su_mask);
   const uint16_t *hu_rank = (const uint16_t *)(img + L.hu_rank);
   const uint16_t *su_rank = (const uint16_t *)(img + L.su_rank);
@@ -125,10 +126,12 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   for (int i = tid; i < P.NB; i += nt) tour_bp[i] = x.tour_bp[i];
   for (int i = tid; i < P.NB; i += nt) bp_len[i] = (uint16_t)(x.bp_off[i + 1] - x.bp_off[i]);
   __syncthreads();
+  uint16_t *t_start = (uint16_t *)(img + L.t_start), *t_end = (uint16_t *)(img + L.t_end);
   if (tid == 0) {
     // BP start positions in tour order (serial prefix over the BPs).
     uint32_t run = 0;
-    for (int g = 0; g < P.NT; ++g)
+    for (int g = 0; g < P.NT; ++g) {
+      t_start[g] = (uint16_t)run;
       for (int j = x.tour_off[g]; j < x.tour_off[g + 1]; ++j) {
         const int b = x.tour_bp[j];
         bp_tour[b] = (uint16_t)g;
@@ -136,6 +139,8 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
         bp_start[b] = (uint16_t)run;
         run += bp_len[b];
       }
+      t_end[g] = (uint16_t)run;
+    }
     *P.best_key = kInfKey;
   }
   __syncthreads();
@@ -165,6 +170,61 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   for (int q = tid; q < P.NF; q += nt) {
     const uint32_t a = q == 0 ? 0u : nb1 + seq[q - 1];
     prec[q].x = P.dist[(size_t)a * P.V + nb1 + seq[q]];
+  }
+  __syncthreads();
+  // Base aggregates per BP, then per tour (every sum is the one the full walk
+  // forms, over the same fields).
+  uint32_t *b_sd = img + L.b_sd, *b_sup = img + L.b_sup, *b_area = img + L.b_area;
+  uint32_t *b_int = img + L.b_int;
+  uint64_t *b_sh = (uint64_t *)(img + L.b_sh);
+  for (int b = tid; b < P.NB; b += nt) {
+    uint32_t sd = 0, sup = 0, ar = 0, in = 0;
+    uint64_t sh = 0;
+    for (int q = bp_start[b]; q < bp_start[b] + bp_len[b]; ++q) {
+      const uint4 r = prec[q];
+      sd += r.y;
+      ar += r.z;
+      sup += r.w;
+      sh += w_q[q];
+      if (q > bp_start[b]) in += r.x;
+    }
+    b_int[b] = in;
+    b_sd[b] = sd;
+    b_sup[b] = sup;
+    b_area[b] = ar;
+    b_sh[b] = sh;
+  }
+  __syncthreads();
+  uint32_t *t_len = img + L.t_len, *t_area = img + L.t_area, *t_msum = img + L.t_msum;
+  uint32_t *t_mcnt = img + L.t_mcnt;
+  uint64_t *t_sh = (uint64_t *)(img + L.t_sh);
+  for (int g = tid; g < P.NT; g += nt) {
+    uint32_t len = 0, ar = 0, ms = 0, mc = 0;
+    uint64_t sh = 0;
+    for (int j = x.tour_off[g]; j < x.tour_off[g + 1]; ++j) {
+      const int b = x.tour_bp[j];
+      ar += b_area[b];
+      sh += b_sh[b];
+      if (bp_len[b]) {
+        ms += b_sd[b] / bp_len[b];
+        mc += 1;
+      }
+    }
+    const int q0 = t_start[g], q1 = t_end[g];
+    if (q1 > q0) {
+      len = f_dhq[seq[q0]] + f_dhq[seq[q1 - 1]];
+      for (int q = q0 + 1; q < q1; ++q) len += prec[q].x;
+    }
+    t_len[g] = len;
+    t_area[g] = ar;
+    t_sh[g] = sh;
+    t_msum[g] = ms;
+    t_mcnt[g] = mc;
+  }
+  if (tid == 0) {
+    uint32_t v = 0;
+    for (int b = 0; b < P.NB; ++b) v += b_sup[b] < demand[b] ? 1u : 0u;
+    img[L.n_viol] = v;
   }
   for (int g = tid; g < P.NT; g += nt) {
     uint64_t hm = 0, lo = 0, hi = 0;
@@ -275,7 +335,8 @@ __device__ void commit_body(const InstParams &P, const View &V, int mode, uint64
     const uint64_t seg_mask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
     const int seg_base = tid & ~(S - 1);
     if (seg_base == 0) {
-      const EvalOut o = eval_candidate(V, P, m, t, S, seg_base, seg_mask);
+      const EvalOut o = (P.flags & kFullWalk) ? eval_candidate<true>(V, P, m, t, S, seg_base, seg_mask)
+                                              : eval_candidate<false>(V, P, m, t, S, seg_base, seg_mask);
       if (t < P.NT) {
         for (uint64_t mm = o.hu_mask; mm; mm &= mm - 1)
           xo.hu_tour[P.hu_id[__ffsll((unsigned long long)mm) - 1]] = (uint16_t)t;
@@ -402,6 +463,7 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
   commit_body(P, V, mode, B.seed, B.index_base + k);
 }
 
+template <bool WALK>
 __global__ __launch_bounds__(256) void k_eval_multi(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   __shared__ uint32_t s_item;
@@ -440,7 +502,7 @@ __global__ __launch_bounds__(256) void k_eval_multi(BatchParams B) {
     uint64_t best = kInfKey;
     for (uint32_t c = c0 + wseg; c < c1; c += segs) {
       const uint64_t w = draw_move(B.seed, c, it, idx, V, P);
-      const CandResult r = eval_one(V, P, w, c, t, S, seg_base, seg_mask, t_star);
+      const CandResult r = eval_one<WALK>(V, P, w, c, t, S, seg_base, seg_mask, t_star);
       best = r.key < best ? r.key : best;
     }
     wave_min_to(best, P.best_key);
@@ -471,46 +533,51 @@ hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, ui
   return hipGetLastError();
 }
 
+// The instantiation for the instance: distance matrix in LDS or not, full
+// walk or delta evaluation.
+template <int MODE, class... A>
+hipError_t launch_k_eval(const InstParams &P, int grid, hipStream_t s, A... a) {
+  const size_t lds = eval_lds_bytes(P);
+  const bool walk = (P.flags & kFullWalk) != 0;
+  if (P.d_in_lds) {
+    if (walk)
+      hipLaunchKernelGGL((k_eval<true, MODE, true>), dim3(grid), dim3(256), lds, s, P, a...);
+    else
+      hipLaunchKernelGGL((k_eval<true, MODE, false>), dim3(grid), dim3(256), lds, s, P, a...);
+  } else {
+    if (walk)
+      hipLaunchKernelGGL((k_eval<false, MODE, true>), dim3(grid), dim3(256), lds, s, P, a...);
+    else
+      hipLaunchKernelGGL((k_eval<false, MODE, false>), dim3(grid), dim3(256), lds, s, P, a...);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
                              uint8_t *flags, int grid, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t lds = eval_lds_bytes(P);
-  if (P.d_in_lds)
-    hipLaunchKernelGGL((k_eval<true, kModeBatch>), dim3(grid), dim3(256), lds, s, P, moves, n,
-                       t_star, 0ull, 0u, key, cost, mk, flags, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_eval<false, kModeBatch>), dim3(grid), dim3(256), lds, s, P, moves, n,
-                       t_star, 0ull, 0u, key, cost, mk, flags, nullptr, nullptr);
-  return hipGetLastError();
+  return launch_k_eval<kModeBatch>(P, grid, s, moves, n, t_star, (uint64_t)0, (uint32_t)0, key, cost,
+                                   mk, flags, (const uint32_t *)nullptr, (const uint32_t *)nullptr);
 }
 
 hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
                               uint32_t inst_index, int grid, hipStream_t s,
                               const uint32_t *run_flag) {
   if (n == 0) return hipSuccess;
-  const size_t lds = eval_lds_bytes(P);
-  if (P.d_in_lds)
-    hipLaunchKernelGGL((k_eval<true, kModeSearch>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr, nullptr, run_flag);
-  else
-    hipLaunchKernelGGL((k_eval<false, kModeSearch>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, nullptr, nullptr, nullptr, nullptr, nullptr, run_flag);
-  return hipGetLastError();
+  return launch_k_eval<kModeSearch>(P, grid, s, (const uint64_t *)nullptr, n, (int64_t)0, seed,
+                                    inst_index, (uint64_t *)nullptr, (float *)nullptr,
+                                    (int32_t *)nullptr, (uint8_t *)nullptr, (const uint32_t *)nullptr,
+                                    run_flag);
 }
 
 hipError_t launch_eval_gather(const InstParams &P, uint64_t seed, const uint32_t *idx, uint32_t n,
                               uint32_t inst_index, uint64_t *key, float *cost, int grid,
                               hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t lds = eval_lds_bytes(P);
-  if (P.d_in_lds)
-    hipLaunchKernelGGL((k_eval<true, kModeGather>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, key, cost, nullptr, nullptr, idx, nullptr);
-  else
-    hipLaunchKernelGGL((k_eval<false, kModeGather>), dim3(grid), dim3(256), lds, s, P, nullptr, n,
-                       0ll, seed, inst_index, key, cost, nullptr, nullptr, idx, nullptr);
-  return hipGetLastError();
+  return launch_k_eval<kModeGather>(P, grid, s, (const uint64_t *)nullptr, n, (int64_t)0, seed,
+                                    inst_index, key, cost, (int32_t *)nullptr, (uint8_t *)nullptr, idx,
+                                    (const uint32_t *)nullptr);
 }
 
 hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t inst_index,
@@ -535,20 +602,26 @@ int eval_occupancy(const InstParams &P, bool search) {
   int nb = 0;
   const size_t lds = eval_lds_bytes(P);
   hipError_t e;
+  const bool walk = (P.flags & kFullWalk) != 0;
   if (P.d_in_lds)
-    e = search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeSearch>, 256, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeBatch>, 256, lds);
+    e = walk ? (search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeSearch, true>, 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeBatch, true>, 256, lds))
+             : (search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeSearch, false>, 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<true, kModeBatch, false>, 256, lds));
   else
-    e = search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeSearch>, 256, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeBatch>, 256, lds);
+    e = walk ? (search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeSearch, true>, 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeBatch, true>, 256, lds))
+             : (search ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeSearch, false>, 256, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval<false, kModeBatch, false>, 256, lds));
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 size_t batch_lds_bytes(uint32_t max_image_words) { return (size_t)round4(max_image_words) * 4; }
 
-int batch_occupancy(size_t lds) {
+int batch_occupancy(size_t lds, bool walk) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi, 256, lds);
+  const hipError_t e = walk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi<true>, 256, lds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi<false>, 256, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -560,7 +633,10 @@ hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s) {
 
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, B.queue);
-  hipLaunchKernelGGL(k_eval_multi, dim3(grid), dim3(256), lds, s, B);
+  if (B.walk)
+    hipLaunchKernelGGL(k_eval_multi<true>, dim3(grid), dim3(256), lds, s, B);
+  else
+    hipLaunchKernelGGL(k_eval_multi<false>, dim3(grid), dim3(256), lds, s, B);
   return hipGetLastError();
 }
 

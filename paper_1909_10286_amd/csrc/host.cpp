@@ -65,6 +65,7 @@ struct Batch {
   uint32_t max_image_words = 0;
   size_t lds = 0;
   int occ = 1;
+  bool walk = false;  // some member asks for the full walk
   bool started = false;
 };
 
@@ -298,6 +299,7 @@ BatchParams batch_params(const Batch &B, const bl_search_params *p) {
   bp.order = B.d_sched + K + 1;
   bp.tile = B.d_sched + 2 * K + 1;
   bp.queue = B.d_sched + 3 * K + 1;
+  bp.walk = B.walk ? 1u : 0u;
   return bp;
 }
 
@@ -481,7 +483,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
       !in->su_cap_kg || !in->su_speed_mph || !in->su_fill_s)
     return fail(c, BL_EINVAL, "null instance array");
   if (in->hu_speed_mph == 0) return fail(c, BL_EINVAL, "hu_speed_mph must be > 0");
-  if (in->flags & ~15u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
+  if (in->flags & ~31u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
   auto I = std::make_unique<Instance>();
   I->NF = NF; I->NB = NB; I->NT = NT; I->NHU = NHU; I->NSU = NSU;
   const int V = 1 + NB + NF;
@@ -581,6 +583,11 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   L.bp_start = al.u16(NB); L.bp_len = al.u16(NB); L.bp_tour = al.u16(NB); L.bp_idx = al.u16(NB);
   L.tour_off = al.u16(NT + 1); L.tour_bp = al.u16(NB);
   L.hu_mask = al.u64(NT); L.su_mask = al.u64(2 * NT);
+  L.t_len = al.u32(NT); L.t_area = al.u32(NT); L.t_sh = al.u64(NT); L.t_msum = al.u32(NT);
+  L.t_mcnt = al.u32(NT); L.t_start = al.u16(NT); L.t_end = al.u16(NT);
+  L.b_sd = al.u32(NB); L.b_sup = al.u32(NB); L.b_area = al.u32(NB); L.b_sh = al.u64(NB);
+  L.b_int = al.u32(NB);
+  L.n_viol = al.u32(1);
   L.total_words = (al.words + 3) & ~3u;
   std::vector<uint32_t> img(L.total_words, 0);
   for (int f = 0; f < NF; ++f) {
@@ -884,12 +891,13 @@ bl_status bl_batch_create(bl_ctx *c, const int32_t *ids, int32_t n_inst, uint32_
       if (ids[j] == ids[k]) return fail(c, BL_EINVAL, "instance %d listed twice", ids[k]);
     B->members.push_back(ids[k]);
     B->max_image_words = std::max(B->max_image_words, I->P.lay.total_words);
+    if (I->P.flags & kFullWalk) B->walk = true;
   }
   B->n = n_cand;
   B->lds = batch_lds_bytes(B->max_image_words);
   if (B->lds > 160 * 1024) return fail(c, BL_EINVAL, "member image exceeds LDS");
   HIP_TRY(c, hipSetDevice(c->device));
-  B->occ = batch_occupancy(B->lds);
+  B->occ = batch_occupancy(B->lds, B->walk);
   const size_t K = B->members.size();
   HIP_TRY(c, hipMalloc(&B->d_inst, K * sizeof(InstParams)));
   if (hipMalloc(&B->d_sched, (3 * K + 2) * sizeof(uint32_t)) != hipSuccess) {
@@ -1283,8 +1291,7 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
       (st = scr_alloc(c, S, T.R, NT * kSurA)) || (st = scr_alloc(c, S, T.U, NT * kSurA)) ||
       (st = scr_alloc(c, S, T.ub6, NT)) || (st = scr_alloc(c, S, T.yb, 2 * NT)) ||
       (st = scr_alloc(c, S, T.nbg, NT)) || (st = scr_alloc(c, S, T.nfg, NT)) ||
-      (st = scr_alloc(c, S, T.tstart, NT)) || (st = scr_alloc(c, S, T.tend, NT)) ||
-      (st = scr_alloc(c, S, T.bsupply, NB)) || (st = scr_alloc(c, S, T.scal, 4)) ||
+      (st = scr_alloc(c, S, T.scal, 4)) ||
       (st = scr_alloc(c, S, T.top_g, 3)) || (st = scr_alloc(c, S, T.desc, chunk)) ||
       (st = scr_alloc(c, S, T.keys, nprop)) || (st = scr_alloc(c, S, T.hist, 2048)) ||
       (st = scr_alloc(c, S, T.sel, 8)) || (st = scr_alloc(c, S, T.blk, 2048)) ||

@@ -586,12 +586,6 @@ __global__ void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
     }
   }
   if (c == 0) {
-    int run = 0;
-    for (int g = 0; g < P.NT; ++g) {
-      T.tstart[g] = run;
-      run += T.nfg[g];
-      T.tend[g] = run;
-    }
     // Three largest completion outputs over active tours (ties to the lower tour).
     int tg[3] = {-1, -1, -1};
     for (int k = 0; k < 3; ++k)
@@ -604,11 +598,6 @@ __global__ void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
       T.top_g[k] = tg[k];
       T.scal[1 + k] = tg[k] >= 0 ? T.yb[2 * tg[k] + 1] : 0.f;
     }
-  }
-  for (int b = c; b < P.NB; b += 64) {
-    uint32_t s = 0;
-    for (int q = V.bp_start[b]; q < V.bp_start[b] + V.bp_len[b]; ++q) s += V.supply[V.seq[q]];
-    T.bsupply[b] = s;
   }
 }
 
@@ -664,109 +653,57 @@ __global__ __launch_bounds__(256) void k_scr_rows(InstParams P, SurDev S, Screen
     for (int k = 0; k < 5; ++k) d.pad[k] = 0;
     int rf[3] = {-1, -1, -1}, rb[3] = {0, 0, 0}, rp[3] = {-1, -1, -1};
     int Ts, Td, newlast_d = -2, newlast_s = -2;  // -2: unchanged, -1: tour empty
+    const Nbrs nb = move_nbrs(V, m);
+    int b0;
     if (m.kind == 0) {
-      const int f = m.v, bs = m.src, bd = m.dst, r = m.r, s = m.slot;
+      const int f = m.v, bs = m.src, bd = m.dst;
       Ts = V.bp_tour[bs];
       Td = V.bp_tour[bd];
-      const int qf = V.pos[f];
-      if (bs != bd && T.bsupply[bs] - V.supply[f] < V.demand[bs]) d.feasible = 0;
-      const int pold = qf - 1 >= T.tstart[Ts] ? V.seq[qf - 1] : -1;
-      const int nold = qf + 1 < T.tend[Ts] ? V.seq[qf + 1] : -1;
-      const int room = V.bp_len[bd] - (bd == bs ? 1 : 0);
-      int pnew, nnew;
-      if (s > 0) {
-        int k = s - 1;
-        if (bd == bs && k >= r) ++k;
-        pnew = V.seq[V.bp_start[bd] + k];
-      } else {
-        int pp = V.bp_start[bd] - 1;
-        if (pp == qf) --pp;
-        pnew = pp >= T.tstart[Td] ? V.seq[pp] : -1;
-      }
-      if (s < room) {
-        int k = s;
-        if (bd == bs && k >= r) ++k;
-        nnew = V.seq[V.bp_start[bd] + k];
-      } else {
-        int pp = V.bp_start[bd] + V.bp_len[bd];
-        if (pp == qf) ++pp;
-        nnew = pp < T.tend[Td] ? V.seq[pp] : -1;
-      }
-      rf[0] = f;
-      rb[0] = bd;
-      rp[0] = pnew;
-      d.bold[0] = (uint16_t)bs;
-      if (nnew >= 0) {
-        rf[1] = nnew;
-        rb[1] = V.fbp[nnew];
-        rp[1] = f;
-        d.bold[1] = (uint16_t)rb[1];
-      }
-      if (nold >= 0 && nold != nnew) {
-        rf[2] = nold;
-        rb[2] = V.fbp[nold];
-        rp[2] = pold;
-        d.bold[2] = (uint16_t)rb[2];
-      }
+      if (bs != bd && V.b_sup[bs] - V.supply[f] < V.demand[bs]) d.feasible = 0;
       add_bp(d, bs, bs == bd ? 0 : -1);
       add_bp(d, bd, bs == bd ? 0 : 1);
       if (Ts != Td) {
         d.dnf[0] = -1;
         d.dnf[1] = 1;
       }
-      if (nnew < 0) newlast_d = f;
-      if (nold < 0) newlast_s = pold;
+      b0 = bd;
+      d.bold[0] = (uint16_t)bs;
     } else {
-      const int b = m.v, s = m.slot, r = m.r;
+      const int b = m.v, len = V.bp_len[b];
       Ts = m.src;
       Td = m.dst;
       d.moved_bp = (uint16_t)b;
       d.dst_tour = (uint16_t)Td;
       add_bp(d, b, 0);
-      const int bs0 = V.bp_start[b], len = V.bp_len[b], bs1 = bs0 + len;
       if (Ts != Td) {
         d.dnf[0] = (int16_t)-len;
         d.dnf[1] = (int16_t)len;
         d.dnb[0] = -1;
         d.dnb[1] = 1;
       }
-      if (len > 0) {
-        const int pold = bs0 - 1 >= T.tstart[Ts] ? V.seq[bs0 - 1] : -1;
-        const int nold = bs1 < T.tend[Ts] ? V.seq[bs1] : -1;
-        const int room = tour_len(V, Td) - (Td == Ts ? 1 : 0);
-        int ip;
-        if (s < room) {
-          int jj = s;
-          if (Td == Ts && jj >= r) ++jj;
-          ip = V.bp_start[V.tour_bp[V.tour_off[Td] + jj]];
-        } else {
-          ip = T.tend[Td];
-        }
-        int pp = ip - 1;
-        if (pp >= bs0 && pp < bs1) pp = bs0 - 1;
-        const int pnew = pp >= T.tstart[Td] ? V.seq[pp] : -1;
-        pp = ip;
-        if (pp >= bs0 && pp < bs1) pp = bs1;
-        const int nnew = pp < T.tend[Td] ? V.seq[pp] : -1;
-        rf[0] = V.seq[bs0];
-        rb[0] = b;
-        rp[0] = pnew;
-        d.bold[0] = (uint16_t)b;
-        if (nnew >= 0) {
-          rf[1] = nnew;
-          rb[1] = V.fbp[nnew];
-          rp[1] = V.seq[bs1 - 1];
-          d.bold[1] = (uint16_t)rb[1];
-        }
-        if (nold >= 0 && nold != nnew) {
-          rf[2] = nold;
-          rb[2] = V.fbp[nold];
-          rp[2] = pold;
-          d.bold[2] = (uint16_t)rb[2];
-        }
-        if (nnew < 0) newlast_d = V.seq[bs1 - 1];
-        if (nold < 0) newlast_s = pold;
+      b0 = b;
+      if (len > 0) d.bold[0] = (uint16_t)b;
+    }
+    // Rows whose route predecessor or BP changes: the moved run's first
+    // field, the field after the insertion point and the one after the gap.
+    if (nb.first >= 0) {
+      rf[0] = nb.first;
+      rb[0] = b0;
+      rp[0] = nb.pnew;
+      if (nb.nnew >= 0) {
+        rf[1] = nb.nnew;
+        rb[1] = V.fbp[nb.nnew];
+        rp[1] = nb.last;
+        d.bold[1] = (uint16_t)rb[1];
       }
+      if (nb.nold >= 0 && nb.nold != nb.nnew) {
+        rf[2] = nb.nold;
+        rb[2] = V.fbp[nb.nold];
+        rp[2] = nb.pold;
+        d.bold[2] = (uint16_t)rb[2];
+      }
+      if (nb.nnew < 0) newlast_d = nb.last;
+      if (nb.nold < 0) newlast_s = nb.pold;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -991,55 +928,59 @@ __global__ void k_topk_count(const uint32_t *keys, uint32_t n, const uint32_t *s
   }
 }
 
-// Exclusive scans of the per-block counts (nblk <= 1024, one block).
-__global__ void k_topk_scan(uint32_t *blk, uint32_t nblk) {
+// Per block: exclusive prefix of the keys equal to the threshold, then of
+// the selected keys (those below it, and the first still-needed ties in index
+// order).  nblk <= 1024, one thread.
+__global__ void k_topk_scan(uint32_t *blk, uint32_t nblk, const uint32_t *sel) {
   if (threadIdx.x == 0) {
-    uint32_t a = 0, b = 0;
+    const uint32_t need_eq = sel[3];
+    uint32_t e = 0, t = 0;
     for (uint32_t i = 0; i < nblk; ++i) {
-      const uint32_t x = blk[i], y = blk[nblk + i];
-      blk[i] = a;
-      blk[nblk + i] = b;
-      a += x;
-      b += y;
+      const uint32_t lt = blk[i], eq = blk[nblk + i];
+      const uint32_t take = e >= need_eq ? 0u : (need_eq - e < eq ? need_eq - e : eq);
+      blk[i] = t;
+      blk[nblk + i] = e;
+      t += lt + take;
+      e += eq;
     }
   }
 }
 
+// The selected indices in ascending order: below the threshold, or equal to
+// it within the first sel[3] such keys.
 __global__ void k_topk_write(const uint32_t *keys, uint32_t n, const uint32_t *sel, const uint32_t *blk,
                              uint32_t *out) {
-  __shared__ uint32_t w_lt[8], w_eq[8];
+  __shared__ uint32_t w_sel[8], w_eq[8];
   uint32_t lo, hi;
   block_counts(n, lo, hi);
-  const uint32_t T = sel[4], need_eq = sel[3], k = sel[5];
-  const uint32_t n_lt = k - need_eq;
-  uint32_t off_lt = blk[blockIdx.x], off_eq = blk[gridDim.x + blockIdx.x];
+  const uint32_t T = sel[4], need_eq = sel[3];
+  uint32_t off_sel = blk[blockIdx.x], off_eq = blk[gridDim.x + blockIdx.x];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   for (uint32_t base = lo; base < hi; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t key = i < hi ? keys[i] : 0xFFFFFFFFu;
     const bool is_lt = i < hi && key < T, is_eq = i < hi && key == T;
-    const uint64_t bl = __ballot(is_lt), be = __ballot(is_eq);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (lane == 0) {
-      w_lt[wave] = (uint32_t)__popcll(bl);
-      w_eq[wave] = (uint32_t)__popcll(be);
-    }
+    // Rank of this tie among the block's ties so far.
+    const uint64_t be = __ballot(is_eq);
+    if (lane == 0) w_eq[wave] = (uint32_t)__popcll(be);
     __syncthreads();
-    uint32_t pl = 0, pe = 0, tl = 0, te = 0;
+    uint32_t pe = 0, te = 0;
     for (int w = 0; w < nw; ++w) {
-      if (w < wave) {
-        pl += w_lt[w];
-        pe += w_eq[w];
-      }
-      tl += w_lt[w];
+      if (w < wave) pe += w_eq[w];
       te += w_eq[w];
     }
-    if (is_lt) out[off_lt + pl + (uint32_t)__popcll(bl & below)] = i;
-    if (is_eq) {
-      const uint32_t r = off_eq + pe + (uint32_t)__popcll(be & below);
-      if (r < need_eq) out[n_lt + r] = i;
+    const bool take = is_lt || (is_eq && off_eq + pe + (uint32_t)__popcll(be & below) < need_eq);
+    const uint64_t bs = __ballot(take);
+    if (lane == 0) w_sel[wave] = (uint32_t)__popcll(bs);
+    __syncthreads();
+    uint32_t ps = 0, ts = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wave) ps += w_sel[w];
+      ts += w_sel[w];
     }
-    off_lt += tl;
+    if (take) out[off_sel + ps + (uint32_t)__popcll(bs & below)] = i;
+    off_sel += ts;
     off_eq += te;
     __syncthreads();
   }
@@ -1177,7 +1118,7 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
     hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(256), 0, s, T.hist, T.sel, pass, k);
   }
   hipLaunchKernelGGL(k_topk_count, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk);
-  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(64), 0, s, T.blk, 1024u);
+  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(64), 0, s, T.blk, 1024u, T.sel);
   hipLaunchKernelGGL(k_topk_write, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk, T.short_idx);
   return hipGetLastError();
 }

@@ -111,6 +111,16 @@ def _inactive_tour_base(inst):
     return x
 
 
+def _empty_bp_base(inst):
+    """BP 0's fields appended to the next BP of the same tour (or of the
+    next tour): BP 0 keeps its place in its tour with no fields."""
+    x = OI.init_solution(inst).copy()
+    dst = next(b for t in x.tours for b in t if b != 0)
+    x.fields[dst] = x.fields[dst] + x.fields[0]
+    x.fields[0] = []
+    return x
+
+
 def _no_hu_base(inst):
     """Tour 0 active without HUs (its HUs moved to tour 1)."""
     x = OI.init_solution(inst)
@@ -135,6 +145,15 @@ CASES = [
     ("batch0", 500, "init", 0, (0, 0), "base"),
     ("batch11", 500, "walk", 0, (0, 0), "base"),
     ("batch42", 500, "init", 0, (0, 0), "big"),
+    # The full walk of every route (BL_FULL_WALK) against the same oracle.
+    ("tiny12", 1000, "inactive", bl.FULL_WALK, (0, 0), "base"),
+    ("mid100", 2085, "init", bl.FULL_WALK, (0, 0), "base"),
+    ("clust500", 129, "walk", bl.FULL_WALK, (2, 3), "big"),
+    # A base with an emptied BP (infeasible): moves that refill it are the only
+    # feasible ones.
+    ("tiny12", 2000, "emptybp", 0, (0, 0), "big"),
+    ("mid100", 2000, "emptybp", 0, (0, 0), "big"),
+    ("mid100", 2000, "emptybp", bl.FULL_WALK, (0, 0), "big"),
 ]
 
 
@@ -143,7 +162,8 @@ def test_evaluate_batch_parity(ctx, name, n, kind, flags, caps, tk):
     _say("evaluate", name, n, kind, flags, caps, tk)
     inst = _instance(name)
     base = {"init": lambda: OI.init_solution(inst), "walk": lambda: _walk_base(inst, OI.init_solution(inst), 5, 40),
-            "inactive": lambda: _inactive_tour_base(inst), "nohu": lambda: _no_hu_base(inst)}[kind]()
+            "inactive": lambda: _inactive_tour_base(inst), "nohu": lambda: _no_hu_base(inst),
+            "emptybp": lambda: _empty_bp_base(inst)}[kind]()
     iid = _setup(ctx, inst, base, flags, *caps)
     fixed = bool(flags & bl.FIXED_FIELD_BP)
     words = oracle_words(inst, base, 42, 3, n, fixed=fixed)
@@ -155,6 +175,29 @@ def test_evaluate_batch_parity(ctx, name, n, kind, flags, caps, tk):
     if kind == "init" and not flags and not name.startswith("batch"):
         # The sample exercises both discarded and ranked candidates.
         assert (orc[3] & bl.CAND_INFEASIBLE).any() and (orc[0] != bl.INF_KEY).any()
+
+
+@pytest.mark.parametrize("name,kind", [("mid100", "walk"), ("clust500", "walk"), ("batch77", "init"),
+                                       ("mid100", "emptybp"), ("tiny12", "inactive")])
+def test_delta_equals_full_walk(ctx, name, kind):
+    """The default evaluation (base aggregates plus the legs a move changes)
+    and the full walk agree bit for bit on 2^16 generated moves."""
+    _say("delta vs walk", name, kind)
+    inst = _instance(name)
+    base = {"init": lambda: OI.init_solution(inst), "walk": lambda: _walk_base(inst, OI.init_solution(inst), 5, 40),
+            "inactive": lambda: _inactive_tour_base(inst), "emptybp": lambda: _empty_bp_base(inst)}[kind]()
+    a = _setup(ctx, inst, base)
+    b = _setup(ctx, inst, base, bl.FULL_WALK)
+    n = 1 << 16
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(a, 77, 5, 0, 0, n, d_mv)
+    words = d_mv.cpu().numpy().view(np.uint64)
+    for t_star in (1 << 40, int(M.evaluate_solution(inst, base).makespan_s) if kind != "emptybp" else 0):
+        ga = _gpu_eval(ctx, a, words, t_star)
+        gb = _gpu_eval(ctx, b, words, t_star)
+        for x, y in zip(ga, gb):
+            assert np.array_equal(x, y)
+    assert (ga[3] & bl.CAND_INFEASIBLE).any()
 
 
 def test_evaluate_invalid_and_ragged(ctx):
@@ -233,7 +276,8 @@ def test_search_trajectory_tiny12(ctx, pool):
 @pytest.mark.parametrize("name,n,iters,eps,flags", [
     ("mid100", 2048, 6, 0.5, 0), ("mid100", 1500, 4, 0.0, bl.FIXED_FIELD_BP),
     ("batch5", 1024, 5, 1.0, 0), ("tiny12", 512, 20, 0.25, bl.GATE_STRICT),
-    ("tiny12", 256, 10, 0.5, bl.GATE_OFF | bl.NO_EMBEDDED_MIN | bl.FIXED_FIELD_BP)])
+    ("tiny12", 256, 10, 0.5, bl.GATE_OFF | bl.NO_EMBEDDED_MIN | bl.FIXED_FIELD_BP),
+    ("mid100", 1024, 4, 0.5, bl.FULL_WALK), ("batch9", 512, 5, 0.5, bl.FULL_WALK)])
 def test_search_trajectory_reduced(ctx, pool, name, n, iters, eps, flags):
     _say("search", name, n, iters, eps, flags)
     inst = _instance(name)

@@ -22,6 +22,7 @@ import pytest
 from oracle import model as M
 from oracle import moves as MV
 from oracle import search as S
+from oracle import surrogate as SG
 
 from paper_1909_10286_amd import bl
 
@@ -76,6 +77,11 @@ def test_screen_scores_match_full_forward(ctx, name, n, k):
     err = np.abs(score[feas] - pred[feas, 0])
     assert err.max() <= tol, (err.max(), tol)
     assert np.array_equal(short, _expected_shortlist(score, k))
+    # And against the float64 reference directly, on a sample (bf16 tolerance
+    # of the full-forward test).
+    idx = np.nonzero(feas)[0][:48]
+    ref = np.array([SG.predict(p, inst, MV.apply_move(base, MV.decode(int(words[i]))), sc)[0] for i in idx])
+    assert (np.abs(score[idx] - ref) <= 2e-2 * np.abs(ref).max() + 1e-3).all()
 
     # The makespan gate: predicted makespan above t_best / t0 + margin drops out.
     margin = float(np.median(pred[feas, 1])) - 1.0   # t0 = t_best: the gate sits at the median
