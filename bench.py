@@ -30,6 +30,43 @@ DESCR = {
 }
 
 
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1909_10286_amd/csrc/eval.hip", "paper_1909_10286_amd/csrc/device.h",
+                  "paper_1909_10286_amd/csrc/bl_internal.h")
+
+
+def kernel_source_digest():
+    """sha256 over the evaluation kernel's sources, to tell whether recorded
+    counter figures still describe the kernel being run."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload):
+    """HBM bytes per evaluation launch from the committed counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
+    readings), or None when there is none or the kernel has changed since."""
+    path = os.path.join(ROOT, "profiles", "k_eval_search_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def lds_bytes_per_candidate(nf, nb, nt, nhu, nsu):
     """Algorithmic LDS bytes of one full evaluation: per field visited 22 B
     (position 2, successor leg 4, field-BP distance 4, area 4, supply 4,
@@ -213,6 +250,7 @@ def main():
     per_launch_s = eval_ms / 1e3 / max(launches, 1)
     bpc = lds_bytes_per_candidate(inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus)
     achieved = bpc * n / per_launch_s / 1e9
+    traffic = recorded_traffic(a.workload) if n == wl["n_cand"] else None
     out = {
         "metric": "candidate evals/s",
         "value": value,
@@ -230,7 +268,8 @@ def main():
                    "n_candidates": n, "instance_seed": 0, "search_seed": seed, "eps": 0.5,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "hbm_frac": None if traffic is None else traffic / per_launch_s / 1e9 / HBM_PEAK_GBS,
                      "kernel": "k_eval (search mode)", "bytes_per_candidate": bpc,
                      "kernel_ms_per_launch": per_launch_s * 1e3},
         "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,

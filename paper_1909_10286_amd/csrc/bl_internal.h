@@ -181,6 +181,8 @@ struct ScreenDev {
   float *scal;               // [4]: predicted base path, top-3 base completion outputs
   int32_t *top_g;            // [3] tours of those top-3 outputs
   ScreenDesc *desc;          // [chunk]
+  uint16_t *phi;             // [3 * chunk][32] changed feature rows, bf16
+  float *P;                  // [3 * chunk][64] their projected rows
   uint32_t *keys;            // [n_prop] order-preserving score bits (0xFFFFFFFF: discarded)
   uint32_t *hist;            // [2048]
   uint32_t *sel;             // [8] radix-select state

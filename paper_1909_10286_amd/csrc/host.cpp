@@ -1273,13 +1273,12 @@ bl_status scr_alloc(bl_ctx *c, Sur &S, T *&p, size_t n) {
   return BL_OK;
 }
 
+constexpr uint32_t kScreenChunk = 1u << 18;
+
 bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, uint32_t k) {
-  // Proposals are screened in chunks whose three changed rows each fit the
-  // surrogate's example buffers (max_examples * NF rows).
-  const uint32_t lim = S.D.cap_ex * (uint32_t)I.NF / 3u;
-  if (lim == 0) return fail(c, BL_EINVAL, "max_examples * n_fields < 3: no room for screening rows");
-  uint32_t chunk = std::min(nprop, lim);
-  if (chunk >= 256u) chunk &= ~255u;
+  // Proposals are screened in chunks of up to 2^18 (three changed rows each:
+  // 64 MB of feature and projected rows per chunk).
+  const uint32_t chunk = std::min(nprop, kScreenChunk);
   if (S.T.keys && S.t_nprop >= nprop && S.t_k >= k && S.t_chunk >= chunk) return BL_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void *p : S.t_allocs) (void)hipFree(p);
@@ -1293,6 +1292,8 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
       (st = scr_alloc(c, S, T.nbg, NT)) || (st = scr_alloc(c, S, T.nfg, NT)) ||
       (st = scr_alloc(c, S, T.scal, 4)) ||
       (st = scr_alloc(c, S, T.top_g, 3)) || (st = scr_alloc(c, S, T.desc, chunk)) ||
+      (st = scr_alloc(c, S, T.phi, (size_t)3 * chunk * kSurK1)) ||
+      (st = scr_alloc(c, S, T.P, (size_t)3 * chunk * kSurA)) ||
       (st = scr_alloc(c, S, T.keys, nprop)) || (st = scr_alloc(c, S, T.hist, 2048)) ||
       (st = scr_alloc(c, S, T.sel, 8)) || (st = scr_alloc(c, S, T.blk, 2048)) ||
       (st = scr_alloc(c, S, T.short_idx, k)) || (st = scr_alloc(c, S, T.short_key, k)) ||

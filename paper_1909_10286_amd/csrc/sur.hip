@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256) void k_scr_rows(InstParams P, SurDev S, Screen
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint16_t *row = S.phi + ((size_t)j * 3 + k) * kSurK1;
+      uint16_t *row = T.phi + ((size_t)j * 3 + k) * kSurK1;
       if (rf[k] >= 0) {
         d.f[k] = (uint16_t)rf[k];
         d.bnew[k] = (uint16_t)rb[k];
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void k_scr_score(InstParams P, SurDev S, Scree
       int qpos[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) qpos[k] = d.f[k] != 0xFFFF ? V.pos[d.f[k]] : 0;
-      const float *pr = S.P + (size_t)j * 3 * kSurA;
+      const float *pr = T.P + (size_t)j * 3 * kSurA;
       for (int c = 0; c < kSurA; ++c) {
         float eo[4], en[4];
 #pragma unroll
@@ -1108,7 +1108,7 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
     hipLaunchKernelGGL(k_scr_rows, dim3(gb), dim3(256), lds_img, s, P, S, T, seed, inst_index, i0, cnt);
     const uint32_t rows = 3 * cnt, tiles = (rows + 15) / 16;
     const uint32_t gf = std::min<uint32_t>((tiles + 3) / 4, (uint32_t)n_cu * 2);
-    hipLaunchKernelGGL(k_sur_fwd, dim3(gf), dim3(256), lds_fwd, s, S, S.phi, rows, S.P, nullptr, nullptr);
+    hipLaunchKernelGGL(k_sur_fwd, dim3(gf), dim3(256), lds_fwd, s, S, T.phi, rows, T.P, nullptr, nullptr);
     hipLaunchKernelGGL(k_scr_score, dim3(gb), dim3(256), 0, s, P, S, T, i0, cnt, mk_margin);
   }
   hipLaunchKernelGGL(k_sur_zero, dim3(8), dim3(256), 0, s, reinterpret_cast<float *>(T.hist), 2048u);
