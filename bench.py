@@ -173,6 +173,125 @@ def bench_batch(a):
     print(json.dumps(out), flush=True)
 
 
+def _accepting(ctx, bl):
+    def accept(inst):
+        iid = ctx.instance_upload(inst)
+        try:
+            ctx.init_solution(iid)
+            return True
+        except bl.BlError as e:
+            if e.status == bl.EINFEASIBLE:
+                return False
+            raise
+    return accept
+
+
+def _timed_run(ctx, stream, iid, x0, iters, step):
+    """Search from x0 for `iters` iterations of `step()`; returns the
+    cumulative seconds after each iteration (HIP events) and the trace's
+    best cost after each iteration (exact, metres)."""
+    import numpy as np
+    import torch
+
+    from paper_1909_10286_amd import bl
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, iters)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(iters):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t = np.array([ev[0].elapsed_time(e) for e in ev[1:]]) / 1e3
+    c = np.array([r["cost_m"] for r in ctx.search_trace(iid)], dtype=np.float64)
+    return t, c
+
+
+def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pairs=1 << 22,
+                      per_base=1 << 16, max_examples=1024, mk_margin=0.05, err_threshold=0.1):
+    """Wall time to within 1 % of the plain search's best cost: the plain
+    search (n_plain exact candidates per iteration) against the screened
+    search (n_prop proposals ranked by the learned screen, the k best
+    evaluated exactly, the plain batch as fallback), on the clust500
+    instance.  The network is trained first on `pairs` exact (candidate,
+    cost) pairs drawn against the bases of a plain trajectory."""
+    import numpy as np
+    import torch
+
+    from paper_1909_10286_amd import bl, inputs
+
+    ctx = bl.Context(0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream)
+    inst = inputs.make_instance("clust500", 0, accept=_accepting(ctx, bl))
+    iid = ctx.instance_upload(inst)
+    x0 = ctx.init_solution(iid)
+    seed, thr = 0, 1 << 31
+
+    # Plain search.
+    tp, cp = _timed_run(ctx, stream, iid, x0, iters, lambda: ctx.search_step(iid, seed, thr, n_plain))
+    target = 1.01 * cp[-1]
+
+    # Training on exact labels along a plain trajectory (its own seed).
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, 0)
+    st = ctx.search_state(iid)
+    w = bl.sur_glorot_weights(inputs.surrogate_init_words(1))
+    sur = ctx.sur_create(iid, w, float(st["cost_best_m"]), float(st["t_best_s"]),
+                         max_examples=max_examples, lr=1e-3)
+    d_mv = torch.empty(per_base, dtype=torch.int64, device="cuda")
+    d_key = torch.empty(per_base, dtype=torch.int64, device="cuda")
+    d_c = torch.empty(per_base, dtype=torch.float32, device="cuda")
+    d_m = torch.empty(per_base, dtype=torch.int32, device="cuda")
+    d_loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_bases = max(1, pairs // per_base)
+    for b in range(n_bases):
+        ctx.search_step(iid, seed + 1, thr, 1 << 16)
+        ctx.generate(iid, seed + 2 + b, 0, 0, 0, per_base, d_mv)
+        ctx.evaluate_batch(iid, d_mv, per_base, 1 << 40, d_key, d_c, d_m, None)
+        last = b == n_bases - 1
+        for j in range(0, per_base, max_examples):
+            m = min(max_examples, per_base - j)
+            ctx.sur_train_step(sur, d_mv[j:], d_c[j:], d_m[j:], m, d_loss if last else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lv = d_loss.cpu().numpy()
+    loss = float(lv[0] / max(lv[1], 1.0))
+
+    # Screened search (one eager call first sizes the screen's buffers).
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, 1)
+    ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold)
+    s0 = ctx.sur_stats(sur)
+    ts, cs = _timed_run(ctx, stream, iid, x0, iters, lambda: ctx.sur_search_step(
+        sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold))
+    s1 = ctx.sur_stats(sur)
+    ctx.close()
+
+    def reach(t, c):
+        hit = np.nonzero(c <= target)[0]
+        return (float(t[hit[0]]), int(hit[0]) + 1) if hit.size else (None, None)
+    tp_hit, ip_hit = reach(tp, cp)
+    ts_hit, is_hit = reach(ts, cs)
+    return {
+        "workload": "clust500 instance; plain: %d exact candidates/iteration; screened: %d proposals -> "
+                    "%d exact (fallback %d); %d iterations each, seed 0, eps 0.5" % (n_plain, n_prop, k, n_plain, iters),
+        "target_km": target / 1e3,
+        "plain": {"best_km": cp[-1] / 1e3, "ms_per_iteration": tp[-1] / iters * 1e3,
+                  "time_to_target_s": tp_hit, "iterations_to_target": ip_hit},
+        "screened": {"best_km": cs[-1] / 1e3, "ms_per_iteration": ts[-1] / iters * 1e3,
+                     "time_to_target_s": ts_hit, "iterations_to_target": is_hit,
+                     "time_to_target_with_training_s": None if ts_hit is None else ts_hit + t_train,
+                     "fallback_iterations": s1["fallbacks"] - s0["fallbacks"],
+                     "last_mean_rel_error": s1["last_error"]},
+        "training": {"pairs": n_bases * per_base, "seconds": t_train, "final_loss": loss,
+                     "examples_per_step": max_examples},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +301,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-screen", action="store_true",
+                    help="skip the plain vs screened wall-time comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scale for the HBM counters)")
     a = ap.parse_args()
@@ -275,11 +396,12 @@ def main():
         "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,
                    "iterations": state["it"], "wall_s": wall},
     }
+    ctx.close()
+    if not a.no_screen and a.workload == "mid100":
+        out["screen"] = screen_comparison()
     if not a.no_cpu_baseline:
-        from oracle import init as OI
         from tests.gpu_common import from_csr
         out["cpu_baseline"] = cpu_baseline(inst, from_csr(x0), a.cpu_sample)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

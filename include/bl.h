@@ -329,10 +329,13 @@ bl_status bl_sur_screen(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
 /* Screened search iteration: the iteration of bl_search_step (eq. (6) base
  * pick, argmin, commit) with the argmin taken over the shortlist of
  * bl_sur_screen, evaluated exactly.  The exact results also judge the
- * screen: when no shortlisted candidate passes the exact gate, or the mean
- * relative error of the predicted path over the shortlisted candidates that
- * have an exact cost exceeds err_threshold, proposals 0 .. n_fallback-1 are
- * evaluated exactly as well (the plain iteration) before the argmin.  Ties
+ * screen: when no shortlisted candidate passes the exact gate, or the
+ * scatter of the predicted path around the exact cost over the shortlisted
+ * candidates that have one (standard deviation of predicted - exact, km,
+ * divided by the mean exact cost; a common offset does not change the
+ * ranking and is not counted) exceeds err_threshold, proposals
+ * 0 .. n_fallback-1 are evaluated exactly as well (the plain iteration)
+ * before the argmin.  Ties
  * and the commit follow bl_search_step.  No host synchronisation.  p->n is
  * ignored.  Async. */
 bl_status bl_sur_search_step(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
@@ -342,7 +345,7 @@ typedef struct {
   uint32_t iterations;   /* screened iterations run                    */
   uint32_t fallbacks;    /* of which evaluated the fallback proposals  */
   uint32_t last_used;    /* shortlisted candidates with an exact cost  */
-  float last_error;      /* last mean relative path error (+inf: none) */
+  float last_error;      /* last scatter of the path error (+inf: none) */
 } bl_sur_stats;
 
 /* Counters of bl_sur_search_step.  Synchronising. */

@@ -63,6 +63,9 @@ struct ImageLayout {
   uint32_t b_area;    // u32 per BP: area
   uint32_t b_sh;      // u64 per BP: shuttle distance
   uint32_t b_int;     // u32 per BP: legs between its consecutive fields
+  uint32_t b_mean;    // u32 per BP: floor(sum D[f][b] / |F_b|), 0 without fields
+  uint32_t b_skip;    // u32 per BP: leg joining its route neighbours once its fields leave
+  uint32_t skip;      // u32 per position: leg joining the field's route neighbours once it leaves
   uint32_t n_viol;    // u32: BPs whose supply is below their demand
   uint32_t static_words, total_words;
 };
@@ -171,7 +174,6 @@ struct ScreenDesc {          // what one proposal changes relative to the base (
 };
 
 struct ScreenDev {
-  float *baseP;              // [NF][64] projected base rows, by base position
   float *Q;                  // [NB][64] sums of the base rows per BP
   float *R;                  // [NT][64] sums over the tour's BPs of the BP means
   float *U;                  // [NT][64] b3 + tour features through W3 rows 128..135

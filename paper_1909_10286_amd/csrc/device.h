@@ -46,7 +46,8 @@ struct View {
   const uint4 *prec;   // per position: {leg in, D[field][BP], area, supply}
   const uint32_t *w_q;  // per position: shuttle distance
   const uint64_t *hu_mask, *su_mask;
-  const uint32_t *t_len, *t_area, *t_msum, *t_mcnt, *b_sd, *b_sup, *b_area, *b_int, *n_viol;
+  const uint32_t *t_len, *t_area, *t_msum, *t_mcnt, *b_sd, *b_sup, *b_area, *b_int, *b_mean, *b_skip,
+      *skip, *n_viol;
   const uint64_t *t_sh, *b_sh;
   const uint16_t *t_start, *t_end;
   const uint32_t *D;
@@ -87,6 +88,9 @@ __device__ __forceinline__ View make_view(const uint32_t *img, const ImageLayout
   v.b_sup = img + L.b_sup;
   v.b_area = img + L.b_area;
   v.b_int = img + L.b_int;
+  v.b_mean = img + L.b_mean;
+  v.b_skip = img + L.b_skip;
+  v.skip = img + L.skip;
   v.n_viol = img + L.n_viol;
   v.t_sh = (const uint64_t *)(img + L.t_sh);
   v.b_sh = (const uint64_t *)(img + L.b_sh);
@@ -323,7 +327,10 @@ __device__ __forceinline__ uint32_t bp_mean(uint32_t sd, uint32_t cnt) { return 
 
 // Tour t of the candidate from the base's aggregates: only the source and
 // destination tours change, by the legs the move cuts and creates and by the
-// moved fields' sums.  Integer results equal the full walk's.
+// moved fields' sums.  Every lane of the segment forms the same changes (the
+// move is uniform over the segment), so the distance-matrix reads of the two
+// created legs are issued together; lane t then applies the source part
+// and/or the destination part.  Integer results equal the full walk's.
 __device__ __forceinline__ void tour_delta(const View &V, const InstParams &P, const Move &m,
                                            const Nbrs &nb, int t, uint32_t &L, uint32_t &A,
                                            uint64_t &sh, uint32_t &msum, uint32_t &mcnt, bool &act) {
@@ -333,76 +340,76 @@ __device__ __forceinline__ void tour_delta(const View &V, const InstParams &P, c
   msum = V.t_msum[t];
   mcnt = V.t_mcnt[t];
   int nf = (int)V.t_end[t] - (int)V.t_start[t];
-  const int Ts = m.kind == 0 ? (int)V.bp_tour[m.src] : m.src;
-  const int Td = m.kind == 0 ? (int)V.bp_tour[m.dst] : m.dst;
-  if ((t == Ts || t == Td) && nb.first >= 0) {
-    int64_t dL = 0;
-    // Legs into and out of the moved run in the base, and the legs created.
-    const bool same_gap = nb.pnew == nb.pold && nb.nnew == nb.nold;
-    uint32_t bridge = 0;
-    if (t == Ts || same_gap) bridge = route_leg(V, P, nb.pold, nb.nold);
-    // A moved BP takes its internal legs along to the other tour.
-    const int64_t inner = (m.kind == 1 && Ts != Td) ? (int64_t)V.b_int[m.v] : 0;
+  if (nb.first >= 0) {  // an empty moved BP changes no route and no sum
+    const bool fm = m.kind == 0;
+    const int Ts = fm ? (int)V.bp_tour[m.src] : m.src;
+    const int Td = fm ? (int)V.bp_tour[m.dst] : m.dst;
+    const bool cross = fm && m.src != m.dst;
+    const size_t nb1 = 1 + (size_t)P.NB;
+    // The created legs and the moved field's distance to its new BP.
+    const uint32_t l_in = route_leg(V, P, nb.pnew, nb.first);
+    const uint32_t l_out = route_leg(V, P, nb.last, nb.nnew);
+    const uint32_t dfd = cross ? V.D[(nb1 + (size_t)m.v) * (size_t)P.V + 1 + (size_t)m.dst] : 0u;
+    // The cut legs (position records) and the leg that closes the gap.
+    const uint32_t bridge = fm ? V.skip[nb.q0] : V.b_skip[m.v];
+    const uint32_t lin = nb.pold < 0 ? V.dhq[nb.first] : V.prec[nb.q0].x;
+    const uint32_t lout = nb.nold < 0 ? V.dhq[nb.last] : V.prec[nb.q1].x;
+    const int64_t inner = fm ? 0 : (int64_t)V.b_int[m.v];
+    uint32_t gap;
+    if (nb.pnew == nb.pold && nb.nnew == nb.nold) {
+      gap = bridge;
+    } else if (nb.pnew < 0 || nb.nnew < 0) {
+      gap = nb.pnew < 0 ? (nb.nnew < 0 ? 0u : V.dhq[nb.nnew]) : V.dhq[nb.pnew];
+    } else {  // consecutive in the base
+      const int qn = V.pos[nb.nnew];
+      gap = V.seq[qn - 1] == nb.pnew ? V.prec[qn].x : route_leg(V, P, nb.pnew, nb.nnew);
+    }
+    // Sums that move with the vertex.
+    uint32_t mv_area, mv_nf;
+    uint64_t sh_out, sh_in;
+    int32_t ms_s = 0, ms_d = 0, mc_s = 0, mc_d = 0;
+    if (fm) {
+      const int f = m.v;
+      mv_area = V.area[f];
+      mv_nf = 1;
+      sh_out = V.w_q[nb.q0];
+      sh_in = cross ? 2ull * (uint64_t)V.nsh[f] * (uint64_t)dfd : sh_out;
+      if (cross) {
+        const int bs = m.src, bd = m.dst;
+        const uint32_t cs = V.bp_len[bs], cd = V.bp_len[bd];
+        ms_s = (int32_t)bp_mean(V.b_sd[bs] - V.prec[nb.q0].y, cs - 1) - (int32_t)V.b_mean[bs];
+        mc_s = cs == 1 ? -1 : 0;
+        ms_d = (int32_t)bp_mean(V.b_sd[bd] + dfd, cd + 1) - (int32_t)V.b_mean[bd];
+        mc_d = cd == 0 ? 1 : 0;
+      }
+    } else {
+      const int b = m.v;
+      mv_area = V.b_area[b];
+      mv_nf = V.bp_len[b];
+      sh_out = sh_in = V.b_sh[b];
+      ms_s = -(int32_t)V.b_mean[b];
+      ms_d = (int32_t)V.b_mean[b];
+      mc_s = -1;
+      mc_d = 1;
+    }
+    int64_t Lx = L;
     if (t == Ts) {
-      const uint32_t lin = nb.pold < 0 ? V.dhq[nb.first] : V.prec[nb.q0].x;
-      const uint32_t lout = nb.nold < 0 ? V.dhq[nb.last] : V.prec[nb.q1].x;
-      dL += (int64_t)bridge - (int64_t)lin - (int64_t)lout - inner;
+      Lx += (int64_t)bridge - (int64_t)lin - (int64_t)lout - inner;
+      A -= mv_area;
+      sh -= sh_out;
+      msum = (uint32_t)((int32_t)msum + ms_s);
+      mcnt = (uint32_t)((int32_t)mcnt + mc_s);
+      nf -= (int)mv_nf;
     }
     if (t == Td) {
-      uint32_t gap;
-      if (same_gap) {
-        gap = bridge;
-      } else if (nb.pnew < 0 || nb.nnew < 0) {
-        gap = route_leg(V, P, nb.pnew, nb.nnew);
-      } else {
-        const int qn = V.pos[nb.nnew];
-        gap = qn > 0 && V.seq[qn - 1] == nb.pnew ? V.prec[qn].x : route_leg(V, P, nb.pnew, nb.nnew);
-      }
-      dL += (int64_t)route_leg(V, P, nb.pnew, nb.first) + (int64_t)route_leg(V, P, nb.last, nb.nnew) -
-            (int64_t)gap + inner;
+      Lx += (int64_t)l_in + (int64_t)l_out - (int64_t)gap + inner;
+      A += mv_area;
+      sh += sh_in;
+      msum = (uint32_t)((int32_t)msum + ms_d);
+      mcnt = (uint32_t)((int32_t)mcnt + mc_d);
+      nf += (int)mv_nf;
     }
-    L = (uint32_t)((int64_t)L + dL);
-    if (m.kind == 0) {
-      const int f = m.v, bs = m.src, bd = m.dst;
-      if (bs != bd) {
-        const uint32_t dfs = V.prec[nb.q0].y;
-        const size_t nb1 = 1 + (size_t)P.NB;
-        const uint32_t dfd = V.D[(nb1 + (size_t)f) * (size_t)P.V + 1 + (size_t)bd];
-        if (t == Ts) {
-          const uint32_t cs = V.bp_len[bs];
-          msum = msum - bp_mean(V.b_sd[bs], cs) + bp_mean(V.b_sd[bs] - dfs, cs - 1);
-          mcnt -= cs == 1 ? 1u : 0u;
-          A -= V.area[f];
-          sh -= V.w_q[nb.q0];
-          nf -= 1;
-        }
-        if (t == Td) {
-          const uint32_t cd = V.bp_len[bd];
-          msum = msum - bp_mean(V.b_sd[bd], cd) + bp_mean(V.b_sd[bd] + dfd, cd + 1);
-          mcnt += cd == 0 ? 1u : 0u;
-          A += V.area[f];
-          sh += 2ull * (uint64_t)V.nsh[f] * (uint64_t)dfd;
-          nf += 1;
-        }
-      }
-    } else if (Ts != Td) {
-      const int b = m.v;
-      const uint32_t mb = bp_mean(V.b_sd[b], V.bp_len[b]);
-      const int len = V.bp_len[b];
-      if (t == Ts) {
-        msum -= mb;
-        mcnt -= 1;
-        A -= V.b_area[b];
-        sh -= V.b_sh[b];
-        nf -= len;
-      } else {
-        msum += mb;
-        mcnt += 1;
-        A += V.b_area[b];
-        sh += V.b_sh[b];
-        nf += len;
-      }
-    }
+    L = (uint32_t)Lx;
   }
   act = nf > 0;
 }
@@ -451,8 +458,9 @@ __device__ __forceinline__ int unpack_min_t(uint64_t k) { return (int)(k & 63); 
 // use a cross-lane permute.
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  // Every lane's partner exists for these patterns, so no old value is kept.
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
@@ -533,9 +541,12 @@ struct EvalOut {
 
 // Evaluate one candidate on the S lanes of a segment (lane t owns tour t).
 // `gate`: 0 = off, 1 = discard when makespan > t_star, 2 = when >= t_star.
-template <bool WALK>
-__device__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move &m, int t,
-                                  int S, int seg_base, uint64_t seg_mask) {
+// SS > 0 fixes the segment width at compile time (the reductions and
+// broadcasts then have no width tests); SS == 0 takes it from S_rt.
+template <bool WALK, int SS>
+__device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move &m, int t,
+                                  int S_rt, int seg_base, uint64_t seg_mask) {
+  const int S = SS > 0 ? SS : S_rt;
   EvalOut o;
   o.flags = 0;
   const bool lane_tour = t < P.NT;
@@ -787,6 +798,21 @@ struct CandResult {
 };
 
 // Full evaluation of move word w as candidate c (all segment lanes call it).
+// The evaluation for the instance's segment width: compile-time widths for
+// up to 16 lanes, the run-time width beyond.
+template <bool WALK>
+__device__ __forceinline__ EvalOut eval_candidate_s(const View &V, const InstParams &P, const Move &m,
+                                                    int t, int S, int seg_base, uint64_t seg_mask) {
+  switch (S) {
+    case 1: return eval_candidate<WALK, 1>(V, P, m, t, S, seg_base, seg_mask);
+    case 2: return eval_candidate<WALK, 2>(V, P, m, t, S, seg_base, seg_mask);
+    case 4: return eval_candidate<WALK, 4>(V, P, m, t, S, seg_base, seg_mask);
+    case 8: return eval_candidate<WALK, 8>(V, P, m, t, S, seg_base, seg_mask);
+    case 16: return eval_candidate<WALK, 16>(V, P, m, t, S, seg_base, seg_mask);
+    default: return eval_candidate<WALK, 0>(V, P, m, t, S, seg_base, seg_mask);
+  }
+}
+
 template <bool WALK>
 __device__ __forceinline__ CandResult eval_one(const View &V, const InstParams &P, uint64_t w,
                                                uint32_t c, int t, int S, int seg_base,
@@ -797,7 +823,7 @@ __device__ __forceinline__ CandResult eval_one(const View &V, const InstParams &
     r.flags = kCandInvalid;
     return r;
   }
-  const EvalOut o = eval_candidate<WALK>(V, P, m, t, S, seg_base, seg_mask);
+  const EvalOut o = eval_candidate_s<WALK>(V, P, m, t, S, seg_base, seg_mask);
   r.flags = o.flags;
   if (o.feasible) {
     r.cost_km = (float)((double)o.cost / 1000.0);

@@ -32,7 +32,7 @@ namespace {
 // (moves drawn for the indices listed in `gather`, per-entry outputs and the
 // argmin).  `run_flag` (nullable): the launch does nothing while it is 0.
 template <bool DLDS, int MODE, bool WALK>
-__global__ __launch_bounds__(256) void k_eval(InstParams P, const uint64_t *__restrict__ moves,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_eval(InstParams P, const uint64_t *__restrict__ moves,
                                               uint32_t n, int64_t t_star_arg, uint64_t seed,
                                               uint32_t inst_index, uint64_t *__restrict__ out_key,
                                               float *__restrict__ out_cost,
@@ -190,9 +190,26 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     }
     b_int[b] = in;
     b_sd[b] = sd;
+    img[L.b_mean + b] = bp_len[b] ? sd / bp_len[b] : 0u;
+    // The leg that closes the route when the BP's fields leave it.
+    uint32_t bridge = 0;
+    if (bp_len[b]) {
+      const int g = bp_tour[b], q0 = bp_start[b], q1 = q0 + bp_len[b];
+      const int po = q0 > (int)t_start[g] ? seq[q0 - 1] : -1, no = q1 < (int)t_end[g] ? seq[q1] : -1;
+      bridge = po < 0 ? (no < 0 ? 0u : f_dhq[no])
+                      : (no < 0 ? f_dhq[po] : P.dist[(size_t)(nb1 + po) * P.V + nb1 + no]);
+    }
+    img[L.b_skip + b] = bridge;
     b_sup[b] = sup;
     b_area[b] = ar;
     b_sh[b] = sh;
+  }
+  // The leg that closes the route when the field at position q leaves it.
+  for (int q = tid; q < P.NF; q += nt) {
+    const int g = bp_tour[fbp[seq[q]]];
+    const int po = q > (int)t_start[g] ? seq[q - 1] : -1, no = q + 1 < (int)t_end[g] ? seq[q + 1] : -1;
+    img[L.skip + q] = po < 0 ? (no < 0 ? 0u : f_dhq[no])
+                             : (no < 0 ? f_dhq[po] : P.dist[(size_t)(nb1 + po) * P.V + nb1 + no]);
   }
   __syncthreads();
   uint32_t *t_len = img + L.t_len, *t_area = img + L.t_area, *t_msum = img + L.t_msum;
@@ -335,8 +352,8 @@ __device__ void commit_body(const InstParams &P, const View &V, int mode, uint64
     const uint64_t seg_mask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
     const int seg_base = tid & ~(S - 1);
     if (seg_base == 0) {
-      const EvalOut o = (P.flags & kFullWalk) ? eval_candidate<true>(V, P, m, t, S, seg_base, seg_mask)
-                                              : eval_candidate<false>(V, P, m, t, S, seg_base, seg_mask);
+      const EvalOut o = (P.flags & kFullWalk) ? eval_candidate<true, 0>(V, P, m, t, S, seg_base, seg_mask)
+                                              : eval_candidate<false, 0>(V, P, m, t, S, seg_base, seg_mask);
       if (t < P.NT) {
         for (uint64_t mm = o.hu_mask; mm; mm &= mm - 1)
           xo.hu_tour[P.hu_id[__ffsll((unsigned long long)mm) - 1]] = (uint16_t)t;

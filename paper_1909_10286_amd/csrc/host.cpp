@@ -586,7 +586,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   L.t_len = al.u32(NT); L.t_area = al.u32(NT); L.t_sh = al.u64(NT); L.t_msum = al.u32(NT);
   L.t_mcnt = al.u32(NT); L.t_start = al.u16(NT); L.t_end = al.u16(NT);
   L.b_sd = al.u32(NB); L.b_sup = al.u32(NB); L.b_area = al.u32(NB); L.b_sh = al.u64(NB);
-  L.b_int = al.u32(NB);
+  L.b_int = al.u32(NB); L.b_mean = al.u32(NB); L.b_skip = al.u32(NB); L.skip = al.u32(NF);
   L.n_viol = al.u32(1);
   L.total_words = (al.words + 3) & ~3u;
   std::vector<uint32_t> img(L.total_words, 0);
@@ -1284,9 +1284,9 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
   for (void *p : S.t_allocs) (void)hipFree(p);
   S.t_allocs.clear();
   ScreenDev &T = S.T;
-  const size_t NF = I.NF, NB = I.NB, NT = I.NT;
+  const size_t NB = I.NB, NT = I.NT;
   bl_status st = BL_OK;
-  if ((st = scr_alloc(c, S, T.baseP, NF * kSurA)) || (st = scr_alloc(c, S, T.Q, NB * kSurA)) ||
+  if ((st = scr_alloc(c, S, T.Q, NB * kSurA)) ||
       (st = scr_alloc(c, S, T.R, NT * kSurA)) || (st = scr_alloc(c, S, T.U, NT * kSurA)) ||
       (st = scr_alloc(c, S, T.ub6, NT)) || (st = scr_alloc(c, S, T.yb, 2 * NT)) ||
       (st = scr_alloc(c, S, T.nbg, NT)) || (st = scr_alloc(c, S, T.nfg, NT)) ||

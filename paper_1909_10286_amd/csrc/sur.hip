@@ -541,25 +541,27 @@ __device__ __forceinline__ float key_score(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-// Base tables from the base's forward rows (example 0); one wave, lane c =
+// Base tables from the base's forward rows (example 0, projected rows in
+// base position order): BP sums, then per tour the sum of BP means, the tour
+// feature term and the head outputs; then the predicted base path and the
+// three largest completion outputs.  One workgroup of 16 waves, lane c =
 // column c.
-__global__ void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
+__global__ __launch_bounds__(1024) void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
   const View V = make_view(P.image, P.lay, P.dist);
-  const int c = threadIdx.x & 63;
-  for (int q = 0; q < P.NF; ++q) T.baseP[q * kSurA + c] = S.P[q * kSurA + c];
-  for (int b = 0; b < P.NB; ++b) {
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int b = w; b < P.NB; b += nw) {
     float s = 0.f;
     const int st = V.bp_start[b], len = V.bp_len[b];
     for (int q = st; q < st + len; ++q) s += S.P[q * kSurA + c];
     T.Q[b * kSurA + c] = s;
   }
+  __syncthreads();
   float w3u[kSurU];
   for (int j = 0; j < kSurU; ++j) w3u[j] = S.W[kSurOffW3 + (kSurH + j) * kSurA + c];
   const float b3 = S.W[kSurOffB3 + c];
   const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
   const float b40 = S.W[kSurOffB4], b41 = S.W[kSurOffB4 + 1];
-  float psum = 0.f;
-  for (int g = 0; g < P.NT; ++g) {
+  for (int g = w; g < P.NT; g += nw) {
     const int nb = tour_len(V, g);
     float R = 0.f;
     int nf = 0;
@@ -582,10 +584,13 @@ __global__ void k_scr_tables(InstParams P, SurDev S, ScreenDev T) {
       T.nbg[g] = nb;
       T.nfg[g] = nf;
       T.ub6[g] = u[6];
-      if (nf > 0) psum += y0;
     }
   }
-  if (c == 0) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float psum = 0.f;
+    for (int g = 0; g < P.NT; ++g)
+      if (T.nfg[g] > 0) psum += T.yb[2 * g];
     // Three largest completion outputs over active tours (ties to the lower tour).
     int tg[3] = {-1, -1, -1};
     for (int k = 0; k < 3; ++k)
@@ -741,75 +746,66 @@ __global__ __launch_bounds__(256) void k_scr_rows(InstParams P, SurDev S, Screen
 
 // Predicted (path, makespan) of proposals i0 .. i0+cnt-1 from their
 // descriptors and projected rows; writes their score keys (predicted path,
-// or discarded when infeasible or above the makespan gate).
+// or discarded when infeasible or above the makespan gate).  One wave per
+// proposal, lane c = embedding column c: every row read is one coalesced
+// 256-byte line.
 __global__ __launch_bounds__(256) void k_scr_score(InstParams P, SurDev S, ScreenDev T, uint32_t i0,
                                                    uint32_t cnt, float mk_margin) {
   const View V = make_view(P.image, P.lay, P.dist);
+  const int c = threadIdx.x & 63;
   const float gate = (float)P.st->t_best * S.inv_t0 + mk_margin;
   const float b40 = S.W[kSurOffB4], b41 = S.W[kSurOffB4 + 1];
-  const float inv_nf = 1.f / (float)P.NF, inv_nb = 1.f / (float)P.NB;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+  const float w3u4 = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c] / (float)P.NF;
+  const float w3u5 = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c] / (float)P.NB;
+  const float w3u6 = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
+  const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t j = wave; j < cnt; j += nwave) {
     const ScreenDesc d = T.desc[j];
     uint32_t key = 0xFFFFFFFFu;
     if (d.feasible) {
-      float y0[2] = {b40, b40}, y1[2] = {b41, b41};
-      int bt[4], ct[4], cb[4], cn[4];
+      // BP means before and after, column c.
+      float eo[4], en[4];
+      int bt[4], ct[4];
+      const float *pr = T.P + (size_t)j * 3 * kSurA;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const int b = d.ab[a];
+        eo[a] = en[a] = 0.f;
         bt[a] = ct[a] = -1;
-        cb[a] = cn[a] = 0;
-        if (b != 0xFFFF) {
-          bt[a] = V.bp_tour[b];
-          ct[a] = b == d.moved_bp ? d.dst_tour : bt[a];
-          cb[a] = V.bp_len[b];
-          cn[a] = cb[a] + d.dcnt[a];
-        }
-      }
-      int qpos[3];
+        const int b = d.ab[a];
+        if (b == 0xFFFF) continue;
+        bt[a] = V.bp_tour[b];
+        ct[a] = b == d.moved_bp ? d.dst_tour : bt[a];
+        const int cb = V.bp_len[b], cn = cb + d.dcnt[a];
+        const float qo = T.Q[b * kSurA + c];
+        float qn = qo;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) qpos[k] = d.f[k] != 0xFFFF ? V.pos[d.f[k]] : 0;
-      const float *pr = T.P + (size_t)j * 3 * kSurA;
-      for (int c = 0; c < kSurA; ++c) {
-        float eo[4], en[4];
+        for (int k = 0; k < 3; ++k) {
+          if (d.f[k] == 0xFFFF) continue;
+          if (d.bold[k] == b) qn -= S.P[(size_t)V.pos[d.f[k]] * kSurA + c];
+          if (d.bnew[k] == b) qn += pr[k * kSurA + c];
+        }
+        eo[a] = cb > 0 ? qo / (float)cb : 0.f;
+        en[a] = cn > 0 ? qn / (float)cn : 0.f;
+      }
+      float y0[2] = {0.f, 0.f}, y1[2] = {0.f, 0.f};
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        if (d.tg[tt] == 0xFFFF) continue;
+        const int g = d.tg[tt];
+        float R = T.R[g * kSurA + c];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          eo[a] = en[a] = 0.f;
-          if (bt[a] < 0) continue;
-          const int b = d.ab[a];
-          const float qo = T.Q[b * kSurA + c];
-          float qn = qo;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            if (d.f[k] == 0xFFFF) continue;
-            if (d.bold[k] == b) qn -= T.baseP[qpos[k] * kSurA + c];
-            if (d.bnew[k] == b) qn += pr[k * kSurA + c];
-          }
-          eo[a] = cb[a] > 0 ? qo / (float)cb[a] : 0.f;
-          en[a] = cn[a] > 0 ? qn / (float)cn[a] : 0.f;
+          if (bt[a] == g) R -= eo[a];
+          if (ct[a] == g) R += en[a];
         }
-        const float w3u4 = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c];
-        const float w3u5 = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c];
-        const float w3u6 = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
-        const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-          if (d.tg[tt] == 0xFFFF) continue;
-          const int g = d.tg[tt];
-          float R = T.R[g * kSurA + c];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            if (bt[a] == g) R -= eo[a];
-            if (ct[a] == g) R += en[a];
-          }
-          const int nbn = T.nbg[g] + d.dnb[tt];
-          const float z = (nbn > 0 ? R / (float)nbn : 0.f) + T.U[g * kSurA + c] +
-                          (float)d.dnf[tt] * inv_nf * w3u4 + (float)d.dnb[tt] * inv_nb * w3u5 +
-                          (d.u6[tt] - T.ub6[g]) * w3u6;
-          const float a = fmaxf(z, 0.f);
-          y0[tt] += a * w40;
-          y1[tt] += a * w41;
-        }
+        const int nbn = T.nbg[g] + d.dnb[tt];
+        const float z = (nbn > 0 ? R / (float)nbn : 0.f) + T.U[g * kSurA + c] + (float)d.dnf[tt] * w3u4 +
+                        (float)d.dnb[tt] * w3u5 + (d.u6[tt] - T.ub6[g]) * w3u6;
+        const float act = fmaxf(z, 0.f);
+        y0[tt] = wave_sum(act * w40) + b40;
+        y1[tt] = wave_sum(act * w41) + b41;
       }
       float pp = T.scal[0];
       float mm = -__builtin_inff();
@@ -831,7 +827,7 @@ __global__ __launch_bounds__(256) void k_scr_score(InstParams P, SurDev S, Scree
       }
       if (mm <= gate) key = score_key(pp);
     }
-    T.keys[i0 + j] = key;
+    if (c == 0) T.keys[i0 + j] = key;
   }
 }
 
@@ -930,20 +926,32 @@ __global__ void k_topk_count(const uint32_t *keys, uint32_t n, const uint32_t *s
 
 // Per block: exclusive prefix of the keys equal to the threshold, then of
 // the selected keys (those below it, and the first still-needed ties in index
-// order).  nblk <= 1024, one thread.
-__global__ void k_topk_scan(uint32_t *blk, uint32_t nblk, const uint32_t *sel) {
-  if (threadIdx.x == 0) {
-    const uint32_t need_eq = sel[3];
-    uint32_t e = 0, t = 0;
-    for (uint32_t i = 0; i < nblk; ++i) {
-      const uint32_t lt = blk[i], eq = blk[nblk + i];
-      const uint32_t take = e >= need_eq ? 0u : (need_eq - e < eq ? need_eq - e : eq);
-      blk[i] = t;
-      blk[nblk + i] = e;
-      t += lt + take;
-      e += eq;
-    }
+// order).  nblk == blockDim.x == 1024, one workgroup.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const uint32_t x = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
   }
+  const uint32_t incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_topk_scan(uint32_t *blk, uint32_t nblk, const uint32_t *sel) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t i = threadIdx.x;
+  const uint32_t need_eq = sel[3];
+  const uint32_t lt = blk[i], eq = blk[nblk + i];
+  const uint32_t e = block_excl_scan(eq, sh);
+  const uint32_t take = e >= need_eq ? 0u : (need_eq - e < eq ? need_eq - e : eq);
+  const uint32_t t = block_excl_scan(lt + take, sh);
+  blk[i] = t;
+  blk[nblk + i] = e;
 }
 
 // The selected indices in ascending order: below the threshold, or equal to
@@ -994,39 +1002,59 @@ __global__ void k_scr_export(const uint32_t *keys, uint32_t n, float *out) {
   }
 }
 
-// Mean relative error of the predicted path on the exactly evaluated
-// shortlist, and the fallback decision (no ranked candidate, or the error
-// above the threshold).  One block.
-__global__ void k_scr_check(InstParams P, SurDev S, ScreenDev T, uint32_t k, float err_thr) {
-  __shared__ float s_err[256];
-  __shared__ uint32_t s_cnt[256];
-  float e = 0.f;
-  uint32_t cnt = 0;
-  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
+// How far the screen's path predictions scatter around the exact costs of
+// the shortlisted candidates: the standard deviation of (predicted - exact)
+// over those with an exact cost, divided by their mean exact cost.  A common
+// offset does not change the ranking, so it is not counted.  Fallback when
+// no shortlisted candidate passed the exact gate or the scatter exceeds the
+// threshold.  Per-block partial sums (double) into part[4 * gridDim.x], then
+// one thread adds them in block order (deterministic).
+__global__ __launch_bounds__(256) void k_scr_check_part(SurDev S, ScreenDev T, uint32_t k, double *part) {
+  __shared__ double s_v[4][256];
+  double r1 = 0.0, r2 = 0.0, ex = 0.0, cnt = 0.0;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
     const float cost = T.short_cost[j];
     const uint32_t key = T.keys[T.short_idx[j]];
     if (!__builtin_isfinite(cost) || key == 0xFFFFFFFFu || cost <= 0.f) continue;
-    const float pred_km = key_score(key) / S.inv_c0 * 1e-3f;
-    e += fabsf(pred_km - cost) / cost;
-    ++cnt;
+    const double r = (double)key_score(key) / (double)S.inv_c0 * 1e-3 - (double)cost;
+    r1 += r;
+    r2 += r * r;
+    ex += (double)cost;
+    cnt += 1.0;
   }
-  s_err[threadIdx.x] = e;
-  s_cnt[threadIdx.x] = cnt;
+  s_v[0][threadIdx.x] = r1;
+  s_v[1][threadIdx.x] = r2;
+  s_v[2][threadIdx.x] = ex;
+  s_v[3][threadIdx.x] = cnt;
   __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] += s_v[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = s_v[threadIdx.x][0];
+}
+
+__global__ void k_scr_check(InstParams P, ScreenDev T, const double *part, uint32_t nblk, float err_thr) {
   if (threadIdx.x == 0) {
-    float te = 0.f;
-    uint32_t tc = 0;
-    for (int i = 0; i < (int)blockDim.x; ++i) {
-      te += s_err[i];
-      tc += s_cnt[i];
+    double r1 = 0.0, r2 = 0.0, ex = 0.0, cnt = 0.0;
+    for (uint32_t i = 0; i < nblk; ++i) {
+      r1 += part[4 * i];
+      r2 += part[4 * i + 1];
+      ex += part[4 * i + 2];
+      cnt += part[4 * i + 3];
     }
-    const float mean = tc ? te / (float)tc : __builtin_inff();
-    const uint32_t fb = (*P.best_key == kInfKey || mean > err_thr) ? 1u : 0u;
+    float scatter = __builtin_inff();
+    if (cnt > 0.0) {
+      const double mean = r1 / cnt, var = r2 / cnt - mean * mean;
+      scatter = (float)(sqrt(var > 0.0 ? var : 0.0) / (ex / cnt));
+    }
+    const uint32_t fb = (*P.best_key == kInfKey || scatter > err_thr) ? 1u : 0u;
     *T.flag = fb;
-    T.stats[0] = mean;
+    T.stats[0] = scatter;
     T.stats[1] += (float)fb;
     T.stats[2] += 1.f;
-    T.stats[3] = (float)tc;
+    T.stats[3] = (float)cnt;
   }
 }
 
@@ -1099,7 +1127,7 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
                          uint32_t chunk, int n_cu, hipStream_t s) {
   hipError_t e = launch_sur_forward(P, S, nullptr, 1, 1, false, n_cu, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scr_tables, dim3(1), dim3(64), 0, s, P, S, T);
+  hipLaunchKernelGGL(k_scr_tables, dim3(1), dim3(1024), 0, s, P, S, T);
   const size_t lds_img = (size_t)round4(P.lay.total_words) * 4;
   const size_t lds_fwd = (size_t)(128 * kLd1 + 128 * kLd2 + 64 * kLd2) * 2 + 256 * 4 + 4 * 16 * kLd2 * 2;
   for (uint32_t i0 = 0; i0 < n_prop; i0 += chunk) {
@@ -1109,7 +1137,8 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
     const uint32_t rows = 3 * cnt, tiles = (rows + 15) / 16;
     const uint32_t gf = std::min<uint32_t>((tiles + 3) / 4, (uint32_t)n_cu * 2);
     hipLaunchKernelGGL(k_sur_fwd, dim3(gf), dim3(256), lds_fwd, s, S, T.phi, rows, T.P, nullptr, nullptr);
-    hipLaunchKernelGGL(k_scr_score, dim3(gb), dim3(256), 0, s, P, S, T, i0, cnt, mk_margin);
+    const uint32_t gs = std::min<uint32_t>((cnt + 3) / 4, (uint32_t)n_cu * 8);
+    hipLaunchKernelGGL(k_scr_score, dim3(gs), dim3(256), 0, s, P, S, T, i0, cnt, mk_margin);
   }
   hipLaunchKernelGGL(k_sur_zero, dim3(8), dim3(256), 0, s, reinterpret_cast<float *>(T.hist), 2048u);
   hipLaunchKernelGGL(k_sur_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(T.sel), 8u);
@@ -1118,7 +1147,7 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
     hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(256), 0, s, T.hist, T.sel, pass, k);
   }
   hipLaunchKernelGGL(k_topk_count, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk);
-  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(64), 0, s, T.blk, 1024u, T.sel);
+  hipLaunchKernelGGL(k_topk_scan, dim3(1), dim3(1024), 0, s, T.blk, 1024u, T.sel);
   hipLaunchKernelGGL(k_topk_write, dim3(1024), dim3(256), 0, s, T.keys, n_prop, T.sel, T.blk, T.short_idx);
   return hipGetLastError();
 }
@@ -1131,7 +1160,12 @@ hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipSt
 
 hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,
                             float err_thr, hipStream_t s) {
-  hipLaunchKernelGGL(k_scr_check, dim3(1), dim3(256), 0, s, P, S, T, k, err_thr);
+  // The radix-select block counts are no longer needed: their buffer holds
+  // the partial sums.
+  const uint32_t nb = std::min<uint32_t>((k + 255) / 256, 256u);  // 4 doubles each fit T.blk
+  double *part = reinterpret_cast<double *>(T.blk);
+  hipLaunchKernelGGL(k_scr_check_part, dim3(nb), dim3(256), 0, s, S, T, k, part);
+  hipLaunchKernelGGL(k_scr_check, dim3(1), dim3(64), 0, s, P, T, part, nb, err_thr);
   return hipGetLastError();
 }
 
