@@ -292,12 +292,89 @@ def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pai
     }
 
 
+def bench_replica(a):
+    """The paper's experiment at its scale (sec. 3.1-3.2, Table 1): fresh
+    seeded replicas of 1200 fields / 20 BPs / 7 tours, Cases 1-4, the epsilon
+    grid {0, .25, .5, .75, 1}, 5000 iterations; the best cost over epsilon per
+    seed and case.  All seeds and cases of one epsilon run as one batch."""
+    import numpy as np
+    import torch
+
+    from paper_1909_10286_amd import bl, inputs
+
+    ctx = bl.Context(0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream)
+    n = a.n or (1 << 14)
+    iters = a.steps
+    seeds = list(range(a.replica_seeds))
+    cases = {2: bl.FIXED_FIELD_BP | bl.NO_EMBEDDED_MIN | bl.GATE_OFF, 3: bl.FIXED_FIELD_BP, 4: 0}
+    grid = [0.0, 0.25, 0.5, 0.75, 1.0]
+    members, case1 = [], {}
+    t0 = time.perf_counter()
+    for sd in seeds:
+        inst = inputs.make_replica_instance(sd, accept=_accepting(ctx, bl))
+        fixed = ctx.instance_upload(inst, flags=bl.NO_EMBEDDED_MIN)
+        x0 = ctx.init_solution(fixed)
+        ctx.solution_upload(fixed, bl.SLOT_BASE, x0)
+        ctx.search_start(fixed, 0)
+        st = ctx.search_state(fixed)
+        case1[sd] = (st["cost_best_m"], st["t_best_s"])
+        for cs, fl in cases.items():
+            members.append((sd, cs, ctx.instance_upload(inst, flags=fl), x0))
+    best = {}
+    eval_s = 0.0
+    for eps in grid:
+        thr = min(int(round(eps * 2.0 ** 32)), 1 << 32)
+        for _, _, iid, x0 in members:
+            ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+        b = ctx.batch_create([m[2] for m in members], n)
+        ctx.batch_start(b, 0)
+        chunk = 50 if iters % 50 == 0 else 1
+        g = ctx.batch_capture(b, 0, thr, chunk)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(iters // chunk):
+            ctx.graph_launch(g)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        eval_s += e0.elapsed_time(e1) / 1e3
+        for sd, cs, iid, _ in members:
+            st = ctx.search_state(iid)
+            key = (sd, cs)
+            if key not in best or st["cost_best_m"] < best[key][0]:
+                best[key] = (st["cost_best_m"], st["t_best_s"], eps)
+    ctx.close()
+    rows = {1: {"cost_km": float(np.mean([case1[sd][0] for sd in seeds])) / 1e3,
+                "worst_completion_h": float(np.mean([case1[sd][1] for sd in seeds])) / 3600}}
+    for cs in cases:
+        c = [best[(sd, cs)][0] for sd in seeds]
+        rows[cs] = {"cost_km": float(np.mean(c)) / 1e3,
+                    "delta_pct": float(np.mean([(best[(sd, cs)][0] / case1[sd][0] - 1) * 100 for sd in seeds])),
+                    "worst_completion_h": float(np.mean([best[(sd, cs)][1] for sd in seeds])) / 3600,
+                    "eps_star": float(np.mean([best[(sd, cs)][2] for sd in seeds]))}
+    total = len(members) * n * iters * len(grid)
+    print(json.dumps({
+        "metric": "candidate evals/s", "value": total / eval_s, "unit": "evals/s", "n_gpus": 1,
+        "steps": iters, "warmup": 0, "ms_per_step": eval_s / (iters * len(grid)) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "paper replica: 1200 fields, 20 BPs, 7 tours, 7 HUs, 14 + 28 SUs, 80 km "
+                               "square; %d seeds x Cases 2-4 per batch, %d candidates/iteration, "
+                               "epsilon grid of 5" % (len(seeds), n),
+                   "parallelism": "single GPU"},
+        "cases": rows, "wall_s": time.perf_counter() - t0}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="mid100", choices=sorted(DESCR) + ["batch256"])
+    ap.add_argument("--workload", default="mid100", choices=sorted(DESCR) + ["batch256", "replica"])
+    ap.add_argument("--replica-seeds", type=int, default=10)
     ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -326,6 +403,8 @@ def main():
         return
     if a.workload == "batch256":
         return bench_batch(a)
+    if a.workload == "replica":
+        return bench_replica(a)
     wl = inputs.WORKLOADS[a.workload]
     n = a.n or wl["n_cand"]
     ctx = bl.Context(0)

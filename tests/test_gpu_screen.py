@@ -173,3 +173,65 @@ def test_screen_rejects_bad_sizes(ctx):
         ctx.sur_screen(sur, 0, 0, 0, 1, d)
     with pytest.raises(bl.BlError):
         ctx.sur_search_step(sur, 0, 0, (1 << 24) + 1, 1, 0)
+
+
+def test_trained_screen_beats_random_shortlist(ctx):
+    """What the trained network gains over the method without it: after a
+    short training on exact labels along a plain trajectory, its shortlist of
+    1/16 of the proposals holds cheaper candidates on average than a random
+    1/16 (the plain method's view of an equal exact budget) and than the
+    untrained network's shortlist.  The gain is real but small: the measured
+    recall of the exact top-k is close to a random subset's."""
+    _say("trained screen gain")
+    inst, st, iid, sur, p, sc = setup(ctx, "mid100", max_examples=512)
+    untrained = ctx.sur_get_weights(sur)
+    ctx.search_start(iid, 0)
+    per_base, bases = 4096, 24
+    d_mv = torch.empty(per_base, dtype=torch.int64, device="cuda")
+    d_key = torch.empty(per_base, dtype=torch.int64, device="cuda")
+    d_c = torch.empty(per_base, dtype=torch.float32, device="cuda")
+    d_m = torch.empty(per_base, dtype=torch.int32, device="cuda")
+    for b in range(bases):
+        ctx.search_step(iid, 77, S.eps_threshold(0.5), 1 << 14)
+        ctx.generate(iid, 1000 + b, 0, 0, 0, per_base, d_mv)
+        ctx.evaluate_batch(iid, d_mv, per_base, 1 << 40, d_key, d_c, d_m, None)
+        for _ in range(3):
+            for j in range(0, per_base, 512):
+                ctx.sur_train_step(sur, d_mv[j:], d_c[j:], d_m[j:], 512)
+    trained = ctx.sur_get_weights(sur)
+    # A fresh base: the initial solution, proposals of iteration 0.
+    ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(st.x_best))
+    ctx.search_start(iid, 0)
+    n, k, seed = 1 << 16, 1 << 12, 3
+    mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(iid, seed, 0, 0, 0, n, mv)
+    kk = torch.empty(n, dtype=torch.int64, device="cuda")
+    cc = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.evaluate_batch(iid, mv, n, 1 << 40, kk, cc, None, None)
+    torch.cuda.synchronize()
+    keys = kk.cpu().numpy().view(np.uint64)
+    cost = cc.cpu().numpy().astype(np.float64)
+    ok = keys != np.uint64(M.INF_KEY)
+    top = set(np.argsort(keys)[:k][ok[np.argsort(keys)[:k]]].tolist())
+
+    def quality(w):
+        ctx.sur_set_weights(sur, w)
+        short, _ = _screen(ctx, sur, seed, 1 << 32, n, k, margin=1e9)
+        rec = len(top & set(short.tolist())) / len(top)
+        sel = short[ok[short]]
+        return rec, cost[sel].mean()
+
+    rec_t, mean_t = quality(trained)
+    rec_u, mean_u = quality(untrained)
+    rng = np.random.default_rng(0)
+    rand = rng.choice(n, k, replace=False)
+    rec_r = len(top & set(rand.tolist())) / len(top)
+    mean_r = cost[rand[ok[rand]]].mean()
+    _say("recall trained %.3f untrained %.3f random %.3f; mean cost trained %.1f untrained %.1f random %.1f"
+         % (rec_t, rec_u, rec_r, mean_t, mean_u, mean_r))
+    # The trained shortlist is cheaper on average than a random one and than
+    # the untrained network's (the standard error of these means is about
+    # 0.05 % of the cost here), and it finds more of the exact top-k than the
+    # untrained network.
+    assert mean_t < 0.998 * mean_r and mean_t < 0.998 * mean_u
+    assert rec_t > rec_u
