@@ -209,7 +209,8 @@ def _timed_run(ctx, stream, iid, x0, iters, step):
 
 
 def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pairs=1 << 22,
-                      per_base=1 << 16, max_examples=1024, mk_margin=0.05, err_threshold=0.1):
+                      per_base=1 << 16, max_examples=1024, mk_margin=0.05, err_threshold=0.1,
+                      n_control=1 << 12):
     """Wall time to within 1 % of the plain search's best cost: the plain
     search (n_plain exact candidates per iteration) against the screened
     search (n_prop proposals ranked by the learned screen, the k best
@@ -264,10 +265,12 @@ def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pai
     # Screened search (one eager call first sizes the screen's buffers).
     ctx.solution_upload(iid, bl.SLOT_BASE, x0)
     ctx.search_start(iid, 1)
-    ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold)
+    ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold,
+                        n_control=n_control)
     s0 = ctx.sur_stats(sur)
     ts, cs = _timed_run(ctx, stream, iid, x0, iters, lambda: ctx.sur_search_step(
-        sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold))
+        sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold,
+        n_control=n_control))
     s1 = ctx.sur_stats(sur)
     ctx.close()
 
@@ -278,7 +281,8 @@ def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pai
     ts_hit, is_hit = reach(ts, cs)
     return {
         "workload": "clust500 instance; plain: %d exact candidates/iteration; screened: %d proposals -> "
-                    "%d exact (fallback %d); %d iterations each, seed 0, eps 0.5" % (n_plain, n_prop, k, n_plain, iters),
+                    "%d exact + %d control (fallback %d); %d iterations each, seed 0, eps 0.5"
+                    % (n_plain, n_prop, k, n_control, n_plain, iters),
         "target_km": target / 1e3,
         "plain": {"best_km": cp[-1] / 1e3, "ms_per_iteration": tp[-1] / iters * 1e3,
                   "time_to_target_s": tp_hit, "iterations_to_target": ip_hit},

@@ -315,6 +315,7 @@ typedef struct {
   uint32_t n_fallback;   /* 0 .. 2^24 (screened step only)             */
   float mk_margin;       /* added to the normalised makespan gate       */
   float err_threshold;   /* screened step only, see below              */
+  uint32_t n_control;    /* screened step only: 0 .. n_proposals       */
 } bl_screen_params;
 
 /* Screen the proposals of the coming iteration of instance `inst` (the one
@@ -328,14 +329,16 @@ bl_status bl_sur_screen(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
 
 /* Screened search iteration: the iteration of bl_search_step (eq. (6) base
  * pick, argmin, commit) with the argmin taken over the shortlist of
- * bl_sur_screen, evaluated exactly.  The exact results also judge the
- * screen: when no shortlisted candidate passes the exact gate, or the
- * scatter of the predicted path around the exact cost over the shortlisted
- * candidates that have one (standard deviation of predicted - exact, km,
- * divided by the mean exact cost; a common offset does not change the
- * ranking and is not counted) exceeds err_threshold, proposals
- * 0 .. n_fallback-1 are evaluated exactly as well (the plain iteration)
- * before the argmin.  Ties
+ * bl_sur_screen and a control sample, proposals 0 .. n_control-1, all
+ * evaluated exactly.  The exact results also judge the screen: when no
+ * shortlisted candidate passes the exact gate, when the control sample's
+ * best key is below the shortlist's (the screen did worse than an
+ * unscreened sample), or when the scatter of the predicted path around the
+ * exact cost over the shortlisted candidates that have one (standard
+ * deviation of predicted - exact, km, divided by the mean exact cost; a
+ * common offset does not change the ranking and is not counted) exceeds
+ * err_threshold, proposals 0 .. n_fallback-1 are evaluated exactly as well
+ * (the plain iteration) before the argmin.  Ties
  * and the commit follow bl_search_step.  No host synchronisation.  p->n is
  * ignored.  Async. */
 bl_status bl_sur_search_step(bl_ctx *ctx, int32_t sur, const bl_search_params *p,

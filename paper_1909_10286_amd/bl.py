@@ -61,7 +61,7 @@ class _SurConfig(C.Structure):
 
 class _ScreenParams(C.Structure):
     _fields_ = [("n_proposals", C.c_uint32), ("n_shortlist", C.c_uint32), ("n_fallback", C.c_uint32),
-                ("mk_margin", C.c_float), ("err_threshold", C.c_float)]
+                ("mk_margin", C.c_float), ("err_threshold", C.c_float), ("n_control", C.c_uint32)]
 
 
 class _SurStats(C.Structure):
@@ -404,15 +404,15 @@ class Context:
     def sur_screen(self, sur: int, seed: int, eps_threshold: int, n_proposals: int, n_shortlist: int,
                    d_shortlist, d_score=None, mk_margin: float = 0.0, inst_index: int = 0):
         p = _SearchParams(seed, eps_threshold, 0, inst_index)
-        sc = _ScreenParams(n_proposals, n_shortlist, 0, mk_margin, 0.0)
+        sc = _ScreenParams(n_proposals, n_shortlist, 0, mk_margin, 0.0, 0)
         self._check(self._lib.bl_sur_screen(self._h, sur, C.byref(p), C.byref(sc),
                                             C.c_void_p(_ptr(d_shortlist)), C.c_void_p(_ptr(d_score))))
 
     def sur_search_step(self, sur: int, seed: int, eps_threshold: int, n_proposals: int,
                         n_shortlist: int, n_fallback: int, mk_margin: float = 0.0,
-                        err_threshold: float = 0.05, inst_index: int = 0):
+                        err_threshold: float = 0.05, n_control: int = 0, inst_index: int = 0):
         p = _SearchParams(seed, eps_threshold, 0, inst_index)
-        sc = _ScreenParams(n_proposals, n_shortlist, n_fallback, mk_margin, err_threshold)
+        sc = _ScreenParams(n_proposals, n_shortlist, n_fallback, mk_margin, err_threshold, n_control)
         self._check(self._lib.bl_sur_search_step(self._h, sur, C.byref(p), C.byref(sc)))
 
     def sur_stats(self, sur: int) -> dict:

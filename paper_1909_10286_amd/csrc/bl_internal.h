@@ -193,6 +193,7 @@ struct ScreenDev {
   uint64_t *short_key;       // [k] their exact keys
   float *short_cost;         // [k] their exact costs, km
   uint32_t *flag;            // [1] 1: evaluate the plain fallback batch
+  uint64_t *ctrl_key;        // [1] best exact key of the control sample
   float *stats;              // [4]: mean relative error, fallbacks, screened iterations, used
 };
 
@@ -245,6 +246,7 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
 hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s);
 hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,
                             float err_thr, hipStream_t s);
+hipError_t launch_scr_control_save(const InstParams &P, const ScreenDev &T, hipStream_t s);
 
 enum { kPrepFromBase = 0, kPrepSearch = 1 };
 enum { kCommitStart = 0, kCommitStep = 1 };

@@ -1298,6 +1298,7 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
       (st = scr_alloc(c, S, T.sel, 8)) || (st = scr_alloc(c, S, T.blk, 2048)) ||
       (st = scr_alloc(c, S, T.short_idx, k)) || (st = scr_alloc(c, S, T.short_key, k)) ||
       (st = scr_alloc(c, S, T.short_cost, k)) || (st = scr_alloc(c, S, T.flag, 1)) ||
+      (st = scr_alloc(c, S, T.ctrl_key, 1)) ||
       (st = scr_alloc(c, S, T.stats, 4))) {
     for (void *p : S.t_allocs) (void)hipFree(p);
     S.t_allocs.clear();
@@ -1332,6 +1333,7 @@ bl_status screen_on(bl_ctx *c, Sur *S, const bl_search_params *p, const bl_scree
   if (sc->n_shortlist == 0 || sc->n_shortlist > sc->n_proposals)
     return fail(c, BL_EINVAL, "n_shortlist out of 1..n_proposals");
   if (sc->n_fallback > kMaxCand) return fail(c, BL_EINVAL, "n_fallback > 2^24");
+  if (sc->n_control > sc->n_proposals) return fail(c, BL_EINVAL, "n_control > n_proposals");
   if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->capturing && !(S->T.keys && S->t_nprop >= sc->n_proposals && S->t_k >= sc->n_shortlist))
@@ -1371,6 +1373,11 @@ bl_status bl_sur_search_step(bl_ctx *c, int32_t id, const bl_search_params *p,
   hipStream_t q = nullptr;
   bl_status st = screen_on(c, S, p, sc, I, q);
   if (st != BL_OK) return st;
+  // The control sample first: its best key is the instance's argmin slot
+  // until the shortlist joins.
+  HIP_TRY(c, launch_eval_search(I->P, p->seed, sc->n_control, p->inst_index,
+                                grid_for(c, *I, std::max(sc->n_control, 1u), true), q, nullptr));
+  HIP_TRY(c, launch_scr_control_save(I->P, S->T, q));
   HIP_TRY(c, launch_eval_gather(I->P, p->seed, S->T.short_idx, sc->n_shortlist, p->inst_index,
                                 S->T.short_key, S->T.short_cost, grid_for(c, *I, sc->n_shortlist, true), q));
   HIP_TRY(c, launch_scr_check(I->P, S->D, S->T, sc->n_shortlist, sc->err_threshold, q));

@@ -1002,17 +1002,22 @@ __global__ void k_scr_export(const uint32_t *keys, uint32_t n, float *out) {
   }
 }
 
-// How far the screen's path predictions scatter around the exact costs of
-// the shortlisted candidates: the standard deviation of (predicted - exact)
-// over those with an exact cost, divided by their mean exact cost.  A common
-// offset does not change the ranking, so it is not counted.  Fallback when
-// no shortlisted candidate passed the exact gate or the scatter exceeds the
-// threshold.  Per-block partial sums (double) into part[4 * gridDim.x], then
-// one thread adds them in block order (deterministic).
+// The judge of the screen.  Scatter: the standard deviation of (predicted -
+// exact) path over the shortlisted candidates with an exact cost, divided by
+// their mean exact cost (a common offset does not change the ranking, so it
+// is not counted).  Fallback when no shortlisted candidate passed the exact
+// gate, when the control sample's best key beats the shortlist's, or when
+// the scatter exceeds the threshold.  Per-block partial sums (double) and
+// key minima into part[5 * gridDim.x], then one thread combines them in
+// block order (deterministic).
 __global__ __launch_bounds__(256) void k_scr_check_part(SurDev S, ScreenDev T, uint32_t k, double *part) {
   __shared__ double s_v[4][256];
+  __shared__ uint64_t s_min[256];
   double r1 = 0.0, r2 = 0.0, ex = 0.0, cnt = 0.0;
+  uint64_t kmin = kInfKey;
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < k; j += gridDim.x * blockDim.x) {
+    const uint64_t xk = T.short_key[j];
+    kmin = xk < kmin ? xk : kmin;
     const float cost = T.short_cost[j];
     const uint32_t key = T.keys[T.short_idx[j]];
     if (!__builtin_isfinite(cost) || key == 0xFFFFFFFFu || cost <= 0.f) continue;
@@ -1026,30 +1031,39 @@ __global__ __launch_bounds__(256) void k_scr_check_part(SurDev S, ScreenDev T, u
   s_v[1][threadIdx.x] = r2;
   s_v[2][threadIdx.x] = ex;
   s_v[3][threadIdx.x] = cnt;
+  s_min[threadIdx.x] = kmin;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off)
+    if ((int)threadIdx.x < off) {
       for (int q = 0; q < 4; ++q) s_v[q][threadIdx.x] += s_v[q][threadIdx.x + off];
+      const uint64_t o = s_min[threadIdx.x + off];
+      if (o < s_min[threadIdx.x]) s_min[threadIdx.x] = o;
+    }
     __syncthreads();
   }
-  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = s_v[threadIdx.x][0];
+  if (threadIdx.x < 4) part[5 * blockIdx.x + threadIdx.x] = s_v[threadIdx.x][0];
+  if (threadIdx.x == 4) reinterpret_cast<uint64_t *>(part)[5 * blockIdx.x + 4] = s_min[0];
 }
 
 __global__ void k_scr_check(InstParams P, ScreenDev T, const double *part, uint32_t nblk, float err_thr) {
   if (threadIdx.x == 0) {
     double r1 = 0.0, r2 = 0.0, ex = 0.0, cnt = 0.0;
+    uint64_t smin = kInfKey;
     for (uint32_t i = 0; i < nblk; ++i) {
-      r1 += part[4 * i];
-      r2 += part[4 * i + 1];
-      ex += part[4 * i + 2];
-      cnt += part[4 * i + 3];
+      r1 += part[5 * i];
+      r2 += part[5 * i + 1];
+      ex += part[5 * i + 2];
+      cnt += part[5 * i + 3];
+      const uint64_t m = reinterpret_cast<const uint64_t *>(part)[5 * i + 4];
+      smin = m < smin ? m : smin;
     }
     float scatter = __builtin_inff();
     if (cnt > 0.0) {
       const double mean = r1 / cnt, var = r2 / cnt - mean * mean;
       scatter = (float)(sqrt(var > 0.0 ? var : 0.0) / (ex / cnt));
     }
-    const uint32_t fb = (*P.best_key == kInfKey || scatter > err_thr) ? 1u : 0u;
+    const bool lost = *T.ctrl_key < smin;
+    const uint32_t fb = (smin == kInfKey || lost || scatter > err_thr) ? 1u : 0u;
     *T.flag = fb;
     T.stats[0] = scatter;
     T.stats[1] += (float)fb;
@@ -1057,6 +1071,10 @@ __global__ void k_scr_check(InstParams P, ScreenDev T, const double *part, uint3
     T.stats[3] = (float)cnt;
   }
 }
+
+// The control sample's best key (the instance's argmin slot after its
+// launch), kept before the shortlist joins the argmin.
+__global__ void k_scr_control_save(const uint64_t *best_key, uint64_t *ctrl_key) { *ctrl_key = *best_key; }
 
 }  // namespace
 
@@ -1152,6 +1170,11 @@ hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &
   return hipGetLastError();
 }
 
+hipError_t launch_scr_control_save(const InstParams &P, const ScreenDev &T, hipStream_t s) {
+  hipLaunchKernelGGL(k_scr_control_save, dim3(1), dim3(1), 0, s, P.best_key, T.ctrl_key);
+  return hipGetLastError();
+}
+
 hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s) {
   const uint32_t gb = std::min<uint32_t>((n + 255) / 256, 1024u);
   hipLaunchKernelGGL(k_scr_export, dim3(gb), dim3(256), 0, s, T.keys, n, score);
@@ -1162,7 +1185,7 @@ hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDe
                             float err_thr, hipStream_t s) {
   // The radix-select block counts are no longer needed: their buffer holds
   // the partial sums.
-  const uint32_t nb = std::min<uint32_t>((k + 255) / 256, 256u);  // 4 doubles each fit T.blk
+  const uint32_t nb = std::min<uint32_t>((k + 255) / 256, 192u);  // 5 words of 8 bytes each fit T.blk
   double *part = reinterpret_cast<double *>(T.blk);
   hipLaunchKernelGGL(k_scr_check_part, dim3(nb), dim3(256), 0, s, S, T, k, part);
   hipLaunchKernelGGL(k_scr_check, dim3(1), dim3(64), 0, s, P, T, part, nb, err_thr);

@@ -24,7 +24,7 @@ from oracle import moves as MV
 from oracle import search as S
 from oracle import surrogate as SG
 
-from paper_1909_10286_amd import bl
+from paper_1909_10286_amd import bl, inputs
 
 from .gpu_common import from_csr, to_csr
 from .sur_common import setup
@@ -95,13 +95,30 @@ def test_screen_scores_match_full_forward(ctx, name, n, k):
     assert np.array_equal(short2, _expected_shortlist(score2, k))
 
 
-def _oracle_subset_step(inst, st, seed, n, eps, subset, force_all=False):
+def _oracle_screened_step(inst, st, seed, n, eps, short, n_control):
+    """The oracle's iteration over the shortlist and the control sample, or
+    over every proposal when the exact results reject the screen (no gated
+    survivor in the shortlist, or the control sample beats it)."""
+    seen = {}
+
+    def key_of(job, i):
+        if i not in seen:
+            seen[i] = S.candidate(job, i)[0]
+        return seen[i]
+
+    decision = {}
+
     def keys(job, nn):
+        smin = min(key_of(job, int(i)) for i in short)
+        cmin = min((key_of(job, i) for i in range(n_control)), default=M.INF_KEY)
+        fallback = smin == M.INF_KEY or cmin < smin
+        decision["fallback"] = fallback
+        subset = range(nn) if fallback else set(int(i) for i in short) | set(range(n_control))
         out = [M.INF_KEY] * nn
-        for i in (range(nn) if force_all else subset):
-            out[int(i)] = S.candidate(job, int(i))[0]
+        for i in subset:
+            out[i] = key_of(job, i)
         return out
-    return S.step(inst, st, seed, n, eps, map_fn=keys)
+    return S.step(inst, st, seed, n, eps, map_fn=keys), decision["fallback"]
 
 
 def _compare(ctx, iid, st, row):
@@ -114,25 +131,24 @@ def _compare(ctx, iid, st, row):
     assert from_csr(ctx.solution_download(iid, bl.SLOT_BEST)) == st.x_best
 
 
-@pytest.mark.parametrize("name,n,k,iters", [("tiny12", 1024, 64, 6), ("mid100", 4096, 96, 3)])
-def test_screened_iteration_matches_oracle_on_shortlist(ctx, name, n, k, iters):
+@pytest.mark.parametrize("name,n,k,n_control,iters", [("tiny12", 1024, 64, 0, 4), ("tiny12", 1024, 64, 48, 6),
+                                                     ("mid100", 1024, 96, 160, 3)])
+def test_screened_iteration_matches_oracle_on_shortlist(ctx, name, n, k, n_control, iters):
     """Each iteration: the shortlist the screen picks, then the oracle's
-    iteration restricted to it (or the plain iteration when the shortlist has
-    no candidate that passes the exact gate)."""
-    _say("screened iteration", name, n, k, iters)
+    iteration over it and the control sample, or the plain iteration when
+    the exact results reject the screen."""
+    _say("screened iteration", name, n, k, n_control, iters)
     inst, st, iid, sur, p, sc = setup(ctx, name)
     ctx.search_start(iid, iters)
     seed, eps = 5, S.eps_threshold(0.5)
     fallbacks = 0
     for it in range(iters):
         short, score = _screen(ctx, sur, seed, eps, n, k, margin=0.5)
-        ctx.sur_search_step(sur, seed, eps, n, k, n, mk_margin=0.5, err_threshold=math.inf)
+        ctx.sur_search_step(sur, seed, eps, n, k, n, mk_margin=0.5, err_threshold=math.inf,
+                            n_control=n_control)
         torch.cuda.synchronize()
-        trial = _oracle_subset_step(inst, st, seed, n, eps, short)
-        if trial.trace[-1].best_key == M.INF_KEY:
-            trial = _oracle_subset_step(inst, st, seed, n, eps, short, force_all=True)
-            fallbacks += 1
-        st = trial
+        st, fb = _oracle_screened_step(inst, st, seed, n, eps, short, n_control)
+        fallbacks += fb
         _compare(ctx, iid, st, it)
     stats = ctx.sur_stats(sur)
     assert stats["iterations"] == iters and stats["fallbacks"] == fallbacks
@@ -173,6 +189,8 @@ def test_screen_rejects_bad_sizes(ctx):
         ctx.sur_screen(sur, 0, 0, 0, 1, d)
     with pytest.raises(bl.BlError):
         ctx.sur_search_step(sur, 0, 0, (1 << 24) + 1, 1, 0)
+    with pytest.raises(bl.BlError):
+        ctx.sur_search_step(sur, 0, 0, 64, 8, 0, n_control=65)  # control beyond the proposals
 
 
 def test_trained_screen_beats_random_shortlist(ctx):
@@ -180,11 +198,15 @@ def test_trained_screen_beats_random_shortlist(ctx):
     short training on exact labels along a plain trajectory, its shortlist of
     1/16 of the proposals holds cheaper candidates on average than a random
     1/16 (the plain method's view of an equal exact budget) and than the
-    untrained network's shortlist.  The gain is real but small: the measured
-    recall of the exact top-k is close to a random subset's."""
+    untrained network's shortlist, and it holds more of the exact top-k.
+    The gain is real but far from what a screen of 2^24 proposals down to
+    2^18 needs: in the search itself an unscreened sample of 2^12 usually
+    beats the shortlist."""
     _say("trained screen gain")
-    inst, st, iid, sur, p, sc = setup(ctx, "mid100", max_examples=512)
-    untrained = ctx.sur_get_weights(sur)
+    inst, st, iid, _, p, sc = setup(ctx, "mid100", max_examples=512)
+    # The library's usual start: Glorot-uniform weights, zero biases.
+    untrained = bl.sur_glorot_weights(inputs.surrogate_init_words(1))
+    sur = ctx.sur_create(iid, untrained, float(st.cost_best), float(st.t_best), max_examples=512)
     ctx.search_start(iid, 0)
     per_base, bases = 4096, 24
     d_mv = torch.empty(per_base, dtype=torch.int64, device="cuda")
@@ -229,9 +251,9 @@ def test_trained_screen_beats_random_shortlist(ctx):
     mean_r = cost[rand[ok[rand]]].mean()
     _say("recall trained %.3f untrained %.3f random %.3f; mean cost trained %.1f untrained %.1f random %.1f"
          % (rec_t, rec_u, rec_r, mean_t, mean_u, mean_r))
-    # The trained shortlist is cheaper on average than a random one and than
-    # the untrained network's (the standard error of these means is about
-    # 0.05 % of the cost here), and it finds more of the exact top-k than the
-    # untrained network.
-    assert mean_t < 0.998 * mean_r and mean_t < 0.998 * mean_u
-    assert rec_t > rec_u
+    # The trained shortlist holds at least twice the random share of the
+    # exact top-k and is cheaper on average than a random one (the standard
+    # error of these means is about 0.05 % of the cost here) and than the
+    # untrained network's.
+    assert rec_t >= 2.0 * max(rec_r, k / n) and rec_t > rec_u
+    assert mean_t < 0.998 * mean_r and mean_t < mean_u
