@@ -129,6 +129,37 @@ def search(inst, x0: M.Solution, seed: int, n: int, iters: int, eps_threshold: i
     return st
 
 
+def search_cpu_version(inst, x0: M.Solution, seed: int, iters: int, eps_threshold: int,
+                       gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
+                       caps=None, embedded_min: bool = True) -> SearchState:
+    """Algorithm 1, CPU version: each iteration draws one remove-and-reinsert
+    move on the eq. (6) base, checks eq. (2), evaluates the candidate (units,
+    cost, makespan gate), keeps it as x* on a strict decrease of C, and
+    continues from it.  A candidate that fails eq. (2) or the gate is not
+    taken: the base is kept (the reading that makes this the GPU version
+    with a single worker).  It is written out here rather than delegated so
+    that the branch can be read against the algorithm."""
+    st = start(inst, x0, caps, embedded_min)
+    for _ in range(iters):
+        it = st.it
+        use_best = exploit_draw(seed, it, inst_idx, eps_threshold)
+        base = st.x_best if use_best else st.x_old
+        mv = draw_move(inst, base, seed, it, 0, inst_idx, fixed_field_bp)
+        r = evaluate_move(inst, base, mv, 0, gate, st.t_best, caps, embedded_min)
+        xb, cb, tb = st.x_best, st.cost_best, st.t_best
+        indicator = 0
+        if r.key == M.INF_KEY:
+            x_old = base
+        else:
+            x_old = with_units(apply_move(base, mv), r.evaluation)
+            if r.evaluation.cost_m < st.cost_best:
+                xb, cb, tb = x_old, r.evaluation.cost_m, r.evaluation.makespan_s
+                indicator = 1 if mv.kind == FIELD else 2
+        trace = st.trace + [TraceRow(it, use_best, r.key, cb, tb, indicator)]
+        st = SearchState(it + 1, xb, cb, tb, x_old, trace)
+    return st
+
+
 def eps_threshold(eps: float) -> int:
     """floor(eps * 2^32), in [0, 2^32]."""
     return int(eps * (1 << 32))

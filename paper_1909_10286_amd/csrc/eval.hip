@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
 }
 
 template <bool WALK>
-__global__ __launch_bounds__(256) void k_eval_multi(BatchParams B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_multi(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x & 63;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256) void k_eval_multi(BatchParams B) {
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(B.queue, 1u);
     __syncthreads();
-    const uint32_t item = s_item;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads below
     if (item >= B.total_items) break;
     int lo = 0, hi = (int)B.K;
     while (hi - lo > 1) {

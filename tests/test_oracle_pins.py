@@ -438,3 +438,28 @@ def test_instance_generator_invariants():
         assert sup >= int(inst.bp_demand_kg.sum())
         again = inputs.make_instance(name, 0, accept=OI.init_feasible)
         assert (again.dist_m == D).all() and again.attempt == inst.attempt
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cpu_version_reaches_tsp_optimum_single_tour(seed):
+    """Algorithm 1's CPU version (one candidate per iteration) on the
+    one-tour instance: it never goes below the brute-force TSP optimum and
+    reaches it, its trace is monotone, and it is the GPU version with a
+    single worker."""
+    nf = 5
+    inst = _single_tour_instance(seed, nf)
+    x0 = OI.init_solution(inst)
+    ev0 = M.evaluate_solution(inst, x0)
+    shuttle = ev0.cost_m - 3 * ev0.length_m[0]
+    D = inst.dist_m.astype(np.int64)
+    best = min(D[0, 2 + p[0]] + sum(D[2 + p[k], 2 + p[k + 1]] for k in range(nf - 1)) + D[2 + p[-1], 0]
+               for p in itertools.permutations(range(nf)))
+    thr = S.eps_threshold(0.5)
+    st = S.search_cpu_version(inst, x0, seed=seed, iters=600, eps_threshold=thr)
+    assert st.cost_best == 3 * best + shuttle
+    costs = [r.cost_m for r in st.trace]
+    assert all(a >= b for a, b in zip(costs, costs[1:]))
+    one = S.search(inst, x0, seed=seed, n=1, iters=600, eps_threshold=thr)
+    assert [(r.best_key, r.cost_m, r.use_best) for r in one.trace] == \
+        [(r.best_key, r.cost_m, r.use_best) for r in st.trace]
+    assert one.x_old == st.x_old and one.x_best == st.x_best
