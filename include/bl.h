@@ -54,6 +54,9 @@ typedef int32_t bl_status;
                                  instead of from the base's per-tour and per-BP
                                  aggregates and the legs the move changes (same
                                  results; the walk is the plain reading of sec. 2.2) */
+#define BL_WIDE_KEYS 32u      /* 64-bit keys in the rebalancing rounds even where the
+                                 instance's time bounds allow 32-bit ones (same
+                                 results) */
 
 /* Per-candidate flags written by bl_evaluate_batch. */
 #define BL_CAND_INFEASIBLE 1u   /* eq. (2) violated; cost and makespan not evaluated */
@@ -78,8 +81,13 @@ typedef struct bl_ctx bl_ctx;
  * 1 <= n_bps <= 4096, 1 <= n_tours <= 64 with n_tours <= n_hus <= 64 (sec. 2.1:
  * the number of tours is bounded by the number of HUs), 1 <= n_sus <= 128.
  * dist_m must be symmetric with a zero diagonal and entries < 2^24.  Every
- * field supply (area * yield, in kg) and their total must stay below 2^32,
- * and the total supply must cover the total demand.  Violations give
+ * field supply (area * yield, in kg), their total, the total area and every
+ * field's shuttle distance 2 n_f D[f][b] must stay below 2^32; the total
+ * supply must cover the total demand; working rates, speeds and the mean SU
+ * capacity must be > 0 and fill times < 2^20 s.  The route-length bound
+ * (n_fields + 1) * max distance must stay below 2^32 m and the path-length
+ * bound (n_hus + n_sus) * route bound + shuttle total below 2^40 m, so that a
+ * cost and a candidate index pack into one 64-bit key.  Violations give
  * BL_EINVAL.
  */
 typedef struct {
@@ -96,7 +104,7 @@ typedef struct {
   const int32_t *xy_m;          /* [2 * V] or NULL: coordinates (learned screen features) */
   const uint16_t *init_hus_per_tour; /* [n_tours] or NULL: initial HU block sizes */
   const uint16_t *init_sus_per_tour; /* [n_tours] or NULL: initial SU block sizes */
-  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* | BL_FULL_WALK */
+  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* | BL_FULL_WALK | BL_WIDE_KEYS */
   uint32_t cap_hu, cap_su;      /* rebalancing round caps; 0 = units + tours */
 } bl_instance;
 

@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbl.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EINFEASIBLE = 0, -1, -2, -3, -4, -5
-FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT, FULL_WALK = 1, 2, 4, 8, 16
+FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT, FULL_WALK, WIDE_KEYS = 1, 2, 4, 8, 16, 32
 CAND_INFEASIBLE, CAND_GATED, CAND_CAP_HU, CAND_CAP_SU, CAND_INVALID, CAND_INF_MAKESPAN = (
     1, 2, 4, 8, 16, 32)
 SLOT_BASE, SLOT_BEST, SLOT_OLD = 0, 1, 2

@@ -18,7 +18,8 @@ constexpr int64_t kInfT = INT64_MAX;
 constexpr int64_t kNegInfT = INT64_MIN;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8, kFullWalk = 16 };
+enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8, kFullWalk = 16,
+                  kWideKeys = 32 };
 enum : uint32_t {
   kCandInfeasible = 1, kCandGated = 2, kCandCapHu = 4, kCandCapSu = 8, kCandInvalid = 16,
   kCandInfMakespan = 32
@@ -97,6 +98,7 @@ struct InstParams {
   uint32_t flags, cap_hu, cap_su, v_hu;
   int32_t seg;        // lanes per candidate: power of two >= NT
   int32_t d_in_lds;   // the distance matrix is staged in LDS too
+  int32_t narrow;     // times provably within (-2^26, 2^26 - 1) s and seg <= 16: 32-bit keys
   ImageLayout lay;
   const uint32_t *dist;
   uint32_t *image;

@@ -478,12 +478,65 @@ __device__ __forceinline__ uint64_t seg_reduce_u64(uint64_t v, int S, Op op) {
   if (S >= 64) v = op(v, (uint64_t)__shfl_xor((unsigned long long)v, 32, S));
   return v;
 }
+// 32-bit keys for instances whose times stay within (-2^26, 2^26 - 1) s and
+// segments of at most 16 lanes: the value + 2^26 in 27 bits above a 5-bit
+// tour field (the infinities take the end codes), so each butterfly step is
+// one DPP move and one max or min.
+constexpr int64_t kNarrowOff = (int64_t)1 << 26;
+constexpr uint32_t kNarrowInf = (1u << 27) - 1u;
+__device__ __forceinline__ uint32_t nclamp(int64_t v) {
+  return v == kInfT ? kNarrowInf : (v == kNegInfT ? 0u : (uint32_t)(v + kNarrowOff));
+}
+__device__ __forceinline__ int64_t nunclamp(uint32_t b) {
+  return b == kNarrowInf ? kInfT : (b == 0u ? kNegInfT : (int64_t)b - kNarrowOff);
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+template <bool MAX>
+__device__ __forceinline__ uint32_t seg_reduce_u32(uint32_t v, int S) {
+  auto op = [](uint32_t a, uint32_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+  if (S >= 2) v = op(v, dpp32<kDppXor1>(v));
+  if (S >= 4) v = op(v, dpp32<kDppXor2>(v));
+  if (S >= 8) v = op(v, dpp32<kDppHalfMirror>(v));
+  if (S >= 16) v = op(v, dpp32<kDppMirror>(v));
+  return v;
+}
+
+// Key operations of the rebalancing rounds, 64-bit (any instance) or 32-bit
+// (narrow instances).
+template <bool NK>
+struct Keys {
+  using K = uint64_t;
+  static constexpr K kNone = 0ull, kNoneMin = ~0ull;
+  __device__ static K pmax(int64_t v, int t) { return pack_max(v, t); }
+  __device__ static K pmin(int64_t v, int t) { return pack_min(v, t); }
+  __device__ static int64_t val(K k) { return unpack_val(k); }
+  __device__ static int tmax(K k) { return unpack_max_t(k); }
+  __device__ static int tmin(K k) { return unpack_min_t(k); }
+};
+template <>
+struct Keys<true> {
+  using K = uint32_t;
+  static constexpr K kNone = 0u, kNoneMin = ~0u;
+  __device__ static K pmax(int64_t v, int t) { return (nclamp(v) << 5) | (uint32_t)(31 - t); }
+  __device__ static K pmin(int64_t v, int t) { return (nclamp(v) << 5) | (uint32_t)t; }
+  __device__ static int64_t val(K k) { return nunclamp(k >> 5); }
+  __device__ static int tmax(K k) { return 31 - (int)(k & 31u); }
+  __device__ static int tmin(K k) { return (int)(k & 31u); }
+};
+
 __device__ __forceinline__ uint64_t seg_max_u64(uint64_t v, int S) {
   return seg_reduce_u64(v, S, [](uint64_t a, uint64_t b) { return a > b ? a : b; });
 }
 __device__ __forceinline__ uint64_t seg_min_u64(uint64_t v, int S) {
   return seg_reduce_u64(v, S, [](uint64_t a, uint64_t b) { return a < b ? a : b; });
 }
+__device__ __forceinline__ uint32_t seg_max_k(uint32_t v, int S) { return seg_reduce_u32<true>(v, S); }
+__device__ __forceinline__ uint32_t seg_min_k(uint32_t v, int S) { return seg_reduce_u32<false>(v, S); }
+__device__ __forceinline__ uint64_t seg_max_k(uint64_t v, int S) { return seg_max_u64(v, S); }
+__device__ __forceinline__ uint64_t seg_min_k(uint64_t v, int S) { return seg_min_u64(v, S); }
 __device__ __forceinline__ uint64_t seg_sum_u64(uint64_t v, int S) {
   return seg_reduce_u64(v, S, [](uint64_t a, uint64_t b) { return a + b; });
 }
@@ -547,6 +600,9 @@ template <bool WALK, int SS>
 __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParams &P, const Move &m, int t,
                                   int S_rt, int seg_base, uint64_t seg_mask) {
   const int S = SS > 0 ? SS : S_rt;
+  // Compile-time widths run only for narrow instances (see eval_candidate_s).
+  using KY = Keys<(SS > 0)>;
+  using K = typename KY::K;
   EvalOut o;
   o.flags = 0;
   const bool lane_tour = t < P.NT;
@@ -646,14 +702,14 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
   if (embedded) {
     int rounds = 0;
     while (true) {
-      const uint64_t kx = seg_max_u64(act ? pack_max(T, t) : 0ull, S);
-      if (kx == 0) break;
-      const int gmax = unpack_max_t(kx);
-      const int64_t top = unpack_val(kx);
-      const uint64_t k2 = seg_max_u64((act && t != gmax) ? pack_max(T, t) : 0ull, S);
-      const bool has2 = k2 != 0;
-      const int g2 = has2 ? unpack_max_t(k2) : -1;
-      const int64_t t2 = has2 ? unpack_val(k2) : 0;
+      const K kx = seg_max_k(act ? KY::pmax(T, t) : KY::kNone, S);
+      if (kx == KY::kNone) break;
+      const int gmax = KY::tmax(kx);
+      const int64_t top = KY::val(kx);
+      const K k2 = seg_max_k((act && t != gmax) ? KY::pmax(T, t) : KY::kNone, S);
+      const bool has2 = k2 != KY::kNone;
+      const int g2 = has2 ? KY::tmax(k2) : -1;
+      const int64_t t2 = has2 ? KY::val(k2) : 0;
       const bool hasu = hm != 0;
       uint64_t dm = seg_ballot(hasu && t != gmax && t != g2, seg_base, seg_mask);
       if (!dm) dm = seg_ballot(hasu && t != gmax, seg_base, seg_mask);
@@ -663,8 +719,8 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
         break;
       }
       const bool donor = (dm >> t) & 1;
-      const uint64_t kn = seg_min_u64(donor ? pack_min(act ? T : kNegInfT, t) : ~0ull, S);
-      const int gmin = unpack_min_t(kn);
+      const K kn = seg_min_k(donor ? KY::pmin(act ? T : kNegInfT, t) : KY::kNoneMin, S);
+      const int gmin = KY::tmin(kn);
       uint64_t cands = bcast_u64(hm, gmin, S);
       const uint64_t lcx = bcast_u64(lc, gmax, S);
       const uint32_t ax = bcast_u32(A, gmax, S);
@@ -681,7 +737,7 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       if (t == gmax) { hm |= 1ull << u; R += ru; }
       if (act) T = tcompl(R);
       ++rounds;
-      const int64_t ntop = unpack_val(seg_max_u64(act ? pack_max(T, t) : 0ull, S));
+      const int64_t ntop = KY::val(seg_max_k(act ? KY::pmax(T, t) : KY::kNone, S));
       if (ntop < top) continue;
       if (t == gmin) { hm |= 1ull << u; R += ru; }
       if (t == gmax) { hm &= ~(1ull << u); R -= ru; }
@@ -689,7 +745,7 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       break;
     }
   }
-  const int64_t tmax = unpack_val(seg_max_u64(act ? pack_max(T, t) : 0ull, S));
+  const int64_t tmax = KY::val(seg_max_k(act ? KY::pmax(T, t) : KY::kNone, S));
   // ---- SU min-max rebalancing, Alg. 2: waiting time ----
   const uint32_t nhu = (uint32_t)__popcll(hm);
   const uint32_t dm_t = n_mean ? sum_mean / n_mean : 0u;
@@ -707,14 +763,14 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
     int64_t W = act ? twait(sm, load) : 0;
     int rounds = 0;
     while (true) {
-      const uint64_t kx = seg_max_u64(act ? pack_max(W, t) : 0ull, S);
-      if (kx == 0) break;
-      const int gmax = unpack_max_t(kx);
-      const int64_t top = unpack_val(kx);
-      const uint64_t k2 = seg_max_u64((act && t != gmax) ? pack_max(W, t) : 0ull, S);
-      const bool has2 = k2 != 0;
-      const int g2 = has2 ? unpack_max_t(k2) : -1;
-      const int64_t w2 = has2 ? unpack_val(k2) : 0;
+      const K kx = seg_max_k(act ? KY::pmax(W, t) : KY::kNone, S);
+      if (kx == KY::kNone) break;
+      const int gmax = KY::tmax(kx);
+      const int64_t top = KY::val(kx);
+      const K k2 = seg_max_k((act && t != gmax) ? KY::pmax(W, t) : KY::kNone, S);
+      const bool has2 = k2 != KY::kNone;
+      const int g2 = has2 ? KY::tmax(k2) : -1;
+      const int64_t w2 = has2 ? KY::val(k2) : 0;
       const bool hasu = !m_empty(sm);
       uint64_t dmk = seg_ballot(hasu && t != gmax && t != g2, seg_base, seg_mask);
       if (!dmk) dmk = seg_ballot(hasu && t != gmax, seg_base, seg_mask);
@@ -724,8 +780,8 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
         break;
       }
       const bool donor = (dmk >> t) & 1;
-      const uint64_t kn = seg_min_u64(donor ? pack_min(act ? W : kNegInfT, t) : ~0ull, S);
-      const int gmin = unpack_min_t(kn);
+      const K kn = seg_min_k(donor ? KY::pmin(act ? W : kNegInfT, t) : KY::kNoneMin, S);
+      const int gmin = KY::tmin(kn);
       M128 cands{bcast_u64(sm.lo, gmin, S), bcast_u64(sm.hi, gmin, S)};
       const M128 mx{bcast_u64(sm.lo, gmax, S), bcast_u64(sm.hi, gmax, S)};
       const uint32_t ldx = bcast_u32(load, gmax, S);
@@ -750,7 +806,7 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       if (t == gmax) { m_set(sm, u); load += fu; }
       if (act) W = twait(sm, load);
       ++rounds;
-      const int64_t ntop = unpack_val(seg_max_u64(act ? pack_max(W, t) : 0ull, S));
+      const int64_t ntop = KY::val(seg_max_k(act ? KY::pmax(W, t) : KY::kNone, S));
       if (ntop < top) continue;
       if (t == gmin) { m_set(sm, u); load += fu; }
       if (t == gmax) { m_clear(sm, u); load -= fu; }
@@ -798,11 +854,13 @@ struct CandResult {
 };
 
 // Full evaluation of move word w as candidate c (all segment lanes call it).
-// The evaluation for the instance's segment width: compile-time widths for
-// up to 16 lanes, the run-time width beyond.
+// The evaluation for the instance's segment width: compile-time widths and
+// 32-bit keys for narrow instances (at most 16 lanes), the run-time width and
+// 64-bit keys otherwise.
 template <bool WALK>
 __device__ __forceinline__ EvalOut eval_candidate_s(const View &V, const InstParams &P, const Move &m,
                                                     int t, int S, int seg_base, uint64_t seg_mask) {
+  if (!P.narrow) return eval_candidate<WALK, 0>(V, P, m, t, S, seg_base, seg_mask);
   switch (S) {
     case 1: return eval_candidate<WALK, 1>(V, P, m, t, S, seg_base, seg_mask);
     case 2: return eval_candidate<WALK, 2>(V, P, m, t, S, seg_base, seg_mask);

@@ -483,7 +483,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
       !in->su_cap_kg || !in->su_speed_mph || !in->su_fill_s)
     return fail(c, BL_EINVAL, "null instance array");
   if (in->hu_speed_mph == 0) return fail(c, BL_EINVAL, "hu_speed_mph must be > 0");
-  if (in->flags & ~31u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
+  if (in->flags & ~63u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
   auto I = std::make_unique<Instance>();
   I->NF = NF; I->NB = NB; I->NT = NT; I->NHU = NHU; I->NSU = NSU;
   const int V = 1 + NB + NF;
@@ -644,6 +644,21 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   size_t dlds_max = 16 * 1024;
   if (const char *env = getenv("BL_D_LDS_MAX_BYTES")) dlds_max = (size_t)strtoull(env, nullptr, 10);
   P.d_in_lds = ((size_t)L.total_words + (size_t)V * V) * 4 <= dlds_max ? 1 : 0;
+  {
+    // Bounds of every completion time (route bound over the HU speed plus the
+    // whole area at the slowest rate) and waiting time (longest round trip at
+    // the slowest SU, or every fill time): when both fit 26 bits and the
+    // segment has at most 16 lanes, the rebalancing keys are 32-bit.
+    uint32_t rmin = ~0u, vmin = ~0u;
+    uint64_t fills = 0;
+    for (uint32_t r : I->hu_rate) rmin = std::min(rmin, r);
+    for (uint32_t v : I->su_speed) vmin = std::min(vmin, v);
+    for (uint32_t f : I->su_fill) fills += f;
+    const double tb = 3600.0 * (double)lmax / (double)in->hu_speed_mph + 3600.0 * (double)tot_area / (double)rmin;
+    const double wb = std::max(7200.0 * (double)dmax / (double)vmin, (double)fills);
+    const double lim = (double)((1ll << 26) - 4);
+    P.narrow = (tb < lim && wb < lim && P.seg <= 16 && !(in->flags & kWideKeys)) ? 1 : 0;
+  }
   P.lay = L;
   P.dist = R->d_dist;
   P.image = R->d_image;

@@ -154,6 +154,11 @@ CASES = [
     ("tiny12", 2000, "emptybp", 0, (0, 0), "big"),
     ("mid100", 2000, "emptybp", 0, (0, 0), "big"),
     ("mid100", 2000, "emptybp", bl.FULL_WALK, (0, 0), "big"),
+    # 64-bit rebalancing keys where 32-bit ones would do.
+    ("tiny12", 1000, "init", bl.WIDE_KEYS, (0, 0), "base"),
+    ("mid100", 2085, "walk", bl.WIDE_KEYS, (0, 0), "big"),
+    ("clust500", 129, "init", bl.WIDE_KEYS | bl.FULL_WALK, (2, 3), "base"),
+    ("batch31", 500, "init", bl.WIDE_KEYS, (1, 1), "big"),
 ]
 
 
@@ -180,23 +185,26 @@ def test_evaluate_batch_parity(ctx, name, n, kind, flags, caps, tk):
 @pytest.mark.parametrize("name,kind", [("mid100", "walk"), ("clust500", "walk"), ("batch77", "init"),
                                        ("mid100", "emptybp"), ("tiny12", "inactive")])
 def test_delta_equals_full_walk(ctx, name, kind):
-    """The default evaluation (base aggregates plus the legs a move changes)
-    and the full walk agree bit for bit on 2^16 generated moves."""
+    """The default evaluation (base aggregates plus the legs a move changes,
+    32-bit rebalancing keys), the full walk and the 64-bit keys agree bit for
+    bit on 2^16 generated moves."""
     _say("delta vs walk", name, kind)
     inst = _instance(name)
     base = {"init": lambda: OI.init_solution(inst), "walk": lambda: _walk_base(inst, OI.init_solution(inst), 5, 40),
             "inactive": lambda: _inactive_tour_base(inst), "emptybp": lambda: _empty_bp_base(inst)}[kind]()
     a = _setup(ctx, inst, base)
     b = _setup(ctx, inst, base, bl.FULL_WALK)
+    w = _setup(ctx, inst, base, bl.WIDE_KEYS)
     n = 1 << 16
     d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
     ctx.generate(a, 77, 5, 0, 0, n, d_mv)
     words = d_mv.cpu().numpy().view(np.uint64)
     for t_star in (1 << 40, int(M.evaluate_solution(inst, base).makespan_s) if kind != "emptybp" else 0):
         ga = _gpu_eval(ctx, a, words, t_star)
-        gb = _gpu_eval(ctx, b, words, t_star)
-        for x, y in zip(ga, gb):
-            assert np.array_equal(x, y)
+        for other in (b, w):
+            go = _gpu_eval(ctx, other, words, t_star)
+            for x, y in zip(ga, go):
+                assert np.array_equal(x, y)
     assert (ga[3] & bl.CAND_INFEASIBLE).any()
 
 
@@ -277,7 +285,8 @@ def test_search_trajectory_tiny12(ctx, pool):
     ("mid100", 2048, 6, 0.5, 0), ("mid100", 1500, 4, 0.0, bl.FIXED_FIELD_BP),
     ("batch5", 1024, 5, 1.0, 0), ("tiny12", 512, 20, 0.25, bl.GATE_STRICT),
     ("tiny12", 256, 10, 0.5, bl.GATE_OFF | bl.NO_EMBEDDED_MIN | bl.FIXED_FIELD_BP),
-    ("mid100", 1024, 4, 0.5, bl.FULL_WALK), ("batch9", 512, 5, 0.5, bl.FULL_WALK)])
+    ("mid100", 1024, 4, 0.5, bl.FULL_WALK), ("batch9", 512, 5, 0.5, bl.FULL_WALK),
+    ("mid100", 1024, 4, 0.5, bl.WIDE_KEYS), ("tiny12", 512, 12, 0.5, bl.WIDE_KEYS | bl.GATE_STRICT)])
 def test_search_trajectory_reduced(ctx, pool, name, n, iters, eps, flags):
     _say("search", name, n, iters, eps, flags)
     inst = _instance(name)
