@@ -38,6 +38,17 @@ __device__ __forceinline__ uint64_t udiv(uint64_t p, uint32_t q) {
   return (uint64_t)((double)p / (double)q);
 }
 
+// floor(n / d) for n < 2^31 and 0 < d < 2^16 from r = 1/d (double): n * r
+// is within 2^-19 of n / d, whose fraction is at most 1 - 2^-16, so the
+// truncation is floor(n / d) or one below it (exact quotients); one check,
+// whose product stays below 2^32, fixes the latter.  r is computed once per
+// divisor by the caller.  (SU loads are below 2^27: fill times < 2^20 s.)
+__device__ __forceinline__ uint32_t udiv_small(uint32_t n, uint32_t d, double r) {
+  uint32_t q = (uint32_t)((double)n * r);
+  if ((q + 1u) * d <= n) ++q;
+  return q;
+}
+
 // --------------------------------------------------------- the LDS view --
 struct View {
   const uint32_t *area, *supply, *nsh, *dhq, *demand, *hu_rate, *su_fill, *su_speed;
@@ -722,7 +733,11 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       const K kn = seg_min_k(donor ? KY::pmin(act ? T : kNegInfT, t) : KY::kNoneMin, S);
       const int gmin = KY::tmin(kn);
       uint64_t cands = bcast_u64(hm, gmin, S);
-      const uint64_t lcx = bcast_u64(lc, gmax, S);
+      uint64_t lcx;
+      if constexpr (SS > 0)  // narrow: the road part of a completion time is < 2^26
+        lcx = bcast_u32((uint32_t)lc, gmax, S);
+      else
+        lcx = bcast_u64(lc, gmax, S);
       const uint32_t ax = bcast_u32(A, gmax, S);
       const uint32_t rx = bcast_u32(R, gmax, S);
       int u = 0;
@@ -733,15 +748,17 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
         if (!has2 || trial < t2 || cands == 0) break;
       }
       const uint32_t ru = V.hu_rate[u];
+      const int64_t T_before = T;
       if (t == gmin) { hm &= ~(1ull << u); R -= ru; }
       if (t == gmax) { hm |= 1ull << u; R += ru; }
       if (act) T = tcompl(R);
       ++rounds;
       const int64_t ntop = KY::val(seg_max_k(act ? KY::pmax(T, t) : KY::kNone, S));
       if (ntop < top) continue;
+      // Not kept: undo.
       if (t == gmin) { hm |= 1ull << u; R += ru; }
       if (t == gmax) { hm &= ~(1ull << u); R -= ru; }
-      if (act) T = tcompl(R);
+      T = T_before;
       break;
     }
   }
@@ -754,10 +771,11 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
     M128 mm = sm;
     while (!m_empty(mm)) load += V.su_fill[m_pop_low(mm)];
   }
+  const double r_nhu = nhu ? 1.0 / (double)nhu : 0.0;
   auto twait = [&](const M128 &msk, uint32_t ld) -> int64_t {
     if (m_empty(msk) || nhu == 0) return kInfT;
     const int s = m_top(msk);
-    return (int64_t)udiv(7200ull * dm_t, V.su_speed[s]) - (int64_t)((ld - V.su_fill[s]) / nhu);
+    return (int64_t)udiv(7200ull * dm_t, V.su_speed[s]) - (int64_t)udiv_small(ld - V.su_fill[s], nhu, r_nhu);
   };
   if (embedded) {
     int64_t W = act ? twait(sm, load) : 0;
@@ -783,11 +801,16 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       const K kn = seg_min_k(donor ? KY::pmin(act ? W : kNegInfT, t) : KY::kNoneMin, S);
       const int gmin = KY::tmin(kn);
       M128 cands{bcast_u64(sm.lo, gmin, S), bcast_u64(sm.hi, gmin, S)};
-      const M128 mx{bcast_u64(sm.lo, gmax, S), bcast_u64(sm.hi, gmax, S)};
+      // g_max's critical SU, load, HU count and mean distance (< 2^24, so it
+      // shares a word with the HU count).
+      const int topx = (int)bcast_u32((uint32_t)(m_empty(sm) ? -1 : m_top(sm)), gmax, S);
       const uint32_t ldx = bcast_u32(load, gmax, S);
-      const uint32_t nhx = bcast_u32(nhu, gmax, S);
-      const uint32_t dmx = bcast_u32(dm_t, gmax, S);
-      const int topx = m_empty(mx) ? -1 : m_top(mx);
+      const uint32_t nd = bcast_u32((nhu << 24) | dm_t, gmax, S);
+      const uint32_t nhx = nd >> 24, dmx = nd & 0xFFFFFFu;
+      // Round trip of g_max's critical SU: the trial's unless the unit tried
+      // outranks it.
+      const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
+      const double r_nhx = nhx ? 1.0 / (double)nhx : 0.0;
       int u = 0;
       while (!m_empty(cands)) {
         u = m_pop_low(cands);
@@ -797,7 +820,8 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
         } else {
           const int s = u > topx ? u : topx;
           const uint32_t ld = ldx + V.su_fill[u];
-          trial = (int64_t)udiv(7200ull * dmx, V.su_speed[s]) - (int64_t)((ld - V.su_fill[s]) / nhx);
+          const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
+          trial = (int64_t)rt - (int64_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
         }
         if (!has2 || trial < w2 || m_empty(cands)) break;
       }
@@ -808,9 +832,9 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       ++rounds;
       const int64_t ntop = KY::val(seg_max_k(act ? KY::pmax(W, t) : KY::kNone, S));
       if (ntop < top) continue;
+      // Not kept: undo (W is not used after the loop).
       if (t == gmin) { m_set(sm, u); load += fu; }
       if (t == gmax) { m_clear(sm, u); load -= fu; }
-      if (act) W = twait(sm, load);
       break;
     }
   }
