@@ -8,9 +8,11 @@ gate), argmin, reconstruction and commit of the winner.  Inputs are seeded
 synthetic instances resident in HBM before the timed region.
 
 Prints one JSON line.  The roofline object prices the evaluation kernel's
-algorithmic LDS bytes per candidate (the full walk) against the LDS peak;
-the cpu_baseline object times the CPU oracle on a bounded sample of the same
-iteration's candidates.
+algorithmic integer operations per candidate against the integer VALU peak
+(the kernel is bound by VALU issue), with its algorithmic LDS bytes (the full
+walk) against the LDS peak and its measured HBM traffic against 8 TB/s beside
+it; the cpu_baseline object times the CPU oracle on a bounded sample of the
+same iteration's candidates.
 """
 import argparse
 import json
@@ -22,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+# 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no FMA or dual
+# issue doubling, unlike the fp32 figure) = 39.3 T lane-ops/s.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic integer lane-operations of one full candidate evaluation (walk,
+# eq. (2), rebalancing rounds, cost), per workload.
+ALU_OPS_PER_CANDIDATE = {"tiny12": 400, "mid100": 1200, "clust500": 4000}
 
 DESCR = {
     "tiny12": "12 fields, 3 BPs, 2 tours, 4 HUs, 8 SUs, 50 km square",
@@ -454,6 +462,7 @@ def main():
     per_launch_s = eval_ms / 1e3 / max(launches, 1)
     bpc = lds_bytes_per_candidate(inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus)
     achieved = bpc * n / per_launch_s / 1e9
+    alu = ALU_OPS_PER_CANDIDATE[a.workload] * n / per_launch_s / 1e12
     traffic = recorded_traffic(a.workload) if n == wl["n_cand"] else None
     out = {
         "metric": "candidate evals/s",
@@ -471,11 +480,15 @@ def main():
         "config": {"workload": "%s: %s, %d candidates/iteration" % (a.workload, DESCR[a.workload], n),
                    "n_candidates": n, "instance_seed": 0, "search_seed": seed, "eps": 0.5,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
-                     "hbm_frac": None if traffic is None else traffic / per_launch_s / 1e9 / HBM_PEAK_GBS,
-                     "kernel": "k_eval (search mode)", "bytes_per_candidate": bpc,
-                     "kernel_ms_per_launch": per_launch_s * 1e3},
+        "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": alu / ALU_PEAK_TOPS, "traffic": traffic,
+                     "kernel": "k_eval (search mode)", "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
+                     "kernel_ms_per_launch": per_launch_s * 1e3,
+                     "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc},
+                     "hbm": None if traffic is None else {
+                         "achieved": traffic / per_launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": traffic / per_launch_s / 1e9 / HBM_PEAK_GBS}},
         "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,
                    "iterations": state["it"], "wall_s": wall},
     }
