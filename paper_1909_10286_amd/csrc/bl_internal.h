@@ -184,9 +184,6 @@ struct ScreenDev {
   int32_t *nbg, *nfg;        // [NT] BP / field counts
   float *scal;               // [4]: predicted base path, top-3 base completion outputs
   int32_t *top_g;            // [3] tours of those top-3 outputs
-  ScreenDesc *desc;          // [chunk]
-  uint16_t *phi;             // [3 * chunk][32] changed feature rows, bf16
-  float *P;                  // [3 * chunk][64] their projected rows
   uint32_t *keys;            // [n_prop] order-preserving score bits (0xFFFFFFFF: discarded)
   uint32_t *hist;            // [2048]
   uint32_t *sel;             // [8] radix-select state
@@ -244,7 +241,8 @@ hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float 
 
 hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
                          uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
-                         uint32_t chunk, int n_cu, hipStream_t s);
+                         int n_cu, hipStream_t s);
+int screen_waves(const InstParams &P);
 hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s);
 hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,
                             float err_thr, hipStream_t s);

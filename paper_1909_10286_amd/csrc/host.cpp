@@ -52,7 +52,7 @@ struct Sur {
   uint32_t step = 0;
   ScreenDev T{};                 // screening buffers, allocated on first use
   std::vector<void *> t_allocs;
-  uint32_t t_nprop = 0, t_k = 0, t_chunk = 0;
+  uint32_t t_nprop = 0, t_k = 0;
 };
 
 struct Batch {
@@ -1288,13 +1288,8 @@ bl_status scr_alloc(bl_ctx *c, Sur &S, T *&p, size_t n) {
   return BL_OK;
 }
 
-constexpr uint32_t kScreenChunk = 1u << 18;
-
 bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, uint32_t k) {
-  // Proposals are screened in chunks of up to 2^18 (three changed rows each:
-  // 64 MB of feature and projected rows per chunk).
-  const uint32_t chunk = std::min(nprop, kScreenChunk);
-  if (S.T.keys && S.t_nprop >= nprop && S.t_k >= k && S.t_chunk >= chunk) return BL_OK;
+  if (S.T.keys && S.t_nprop >= nprop && S.t_k >= k) return BL_OK;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (void *p : S.t_allocs) (void)hipFree(p);
   S.t_allocs.clear();
@@ -1306,9 +1301,7 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
       (st = scr_alloc(c, S, T.ub6, NT)) || (st = scr_alloc(c, S, T.yb, 2 * NT)) ||
       (st = scr_alloc(c, S, T.nbg, NT)) || (st = scr_alloc(c, S, T.nfg, NT)) ||
       (st = scr_alloc(c, S, T.scal, 4)) ||
-      (st = scr_alloc(c, S, T.top_g, 3)) || (st = scr_alloc(c, S, T.desc, chunk)) ||
-      (st = scr_alloc(c, S, T.phi, (size_t)3 * chunk * kSurK1)) ||
-      (st = scr_alloc(c, S, T.P, (size_t)3 * chunk * kSurA)) ||
+      (st = scr_alloc(c, S, T.top_g, 3)) ||
       (st = scr_alloc(c, S, T.keys, nprop)) || (st = scr_alloc(c, S, T.hist, 2048)) ||
       (st = scr_alloc(c, S, T.sel, 8)) || (st = scr_alloc(c, S, T.blk, 2048)) ||
       (st = scr_alloc(c, S, T.short_idx, k)) || (st = scr_alloc(c, S, T.short_key, k)) ||
@@ -1324,7 +1317,6 @@ bl_status screen_buffers(bl_ctx *c, Sur &S, const Instance &I, uint32_t nprop, u
   HIP_TRY(c, hipMemset(T.flag, 0, 4));
   S.t_nprop = nprop;
   S.t_k = k;
-  S.t_chunk = chunk;
   return BL_OK;
 }
 
@@ -1353,13 +1345,14 @@ bl_status screen_on(bl_ctx *c, Sur *S, const bl_search_params *p, const bl_scree
   HIP_TRY(c, hipSetDevice(c->device));
   if (c->capturing && !(S->T.keys && S->t_nprop >= sc->n_proposals && S->t_k >= sc->n_shortlist))
     return fail(c, BL_ESTATE, "run one screened call of this size before capturing it");
+  if (screen_waves(I->P) == 0)
+    return fail(c, BL_EINVAL, "instance too large for the screen's LDS layout (image + BP and tour tables)");
   bl_status st = screen_buffers(c, *S, *I, sc->n_proposals, sc->n_shortlist);
   if (st != BL_OK) return st;
-  const uint32_t chunk = std::min(S->t_chunk, sc->n_proposals);
   q = work_stream(c);
   HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
   HIP_TRY(c, launch_screen(I->P, S->D, S->T, p->seed, p->inst_index, sc->n_proposals, sc->n_shortlist,
-                           sc->mk_margin, chunk, c->n_cu, q));
+                           sc->mk_margin, c->n_cu, q));
   return BL_OK;
 }
 

@@ -606,228 +606,572 @@ __global__ __launch_bounds__(1024) void k_scr_tables(InstParams P, SurDev S, Scr
   }
 }
 
-__device__ __forceinline__ void feature_row(const View &V, const InstParams &P, const SurDev &S,
-                                            uint16_t *dst, int f, int b, int pred) {
+// The 16 features of field f served from BP b after route predecessor pred
+// (-1: the tour's first field, reached from HQ).
+__device__ __forceinline__ void feature_vals(const View &V, const InstParams &P, const SurDev &S,
+                                             int f, int b, int pred, float v[16]) {
   const int nb1 = 1 + P.NB;
   const size_t Vn = (size_t)P.V;
   const float *fs = S.fstat + (size_t)f * 8;
   const uint32_t dfb = V.D[(size_t)(nb1 + f) * Vn + 1 + b];
   const uint32_t leg = pred < 0 ? V.dhq[f] : V.D[(size_t)(nb1 + pred) * Vn + nb1 + f];
-  float v[16] = {fs[0], fs[1], fs[2], fs[3], S.bxy[2 * b], S.bxy[2 * b + 1],
-                 (float)dfb * S.inv_ds, (float)leg * S.inv_ds, fs[5] * (float)dfb, fs[4],
-                 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  write_row(dst, v);
+  v[0] = fs[0];
+  v[1] = fs[1];
+  v[2] = fs[2];
+  v[3] = fs[3];
+  v[4] = S.bxy[2 * b];
+  v[5] = S.bxy[2 * b + 1];
+  v[6] = (float)dfb * S.inv_ds;
+  v[7] = (float)leg * S.inv_ds;
+  v[8] = fs[5] * (float)dfb;
+  v[9] = fs[4];
+  for (int j = 10; j < 16; ++j) v[j] = 0.f;
 }
 
 __device__ __forceinline__ void add_bp(ScreenDesc &d, int b, int dc) {
+  bool done = false;
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
-    if (d.ab[a] == (uint16_t)b) {
+    if (!done && d.ab[a] == (uint16_t)b) {
       d.dcnt[a] += (int16_t)dc;
-      return;
-    }
-    if (d.ab[a] == 0xFFFF) {
+      done = true;
+    } else if (!done && d.ab[a] == 0xFFFF) {
       d.ab[a] = (uint16_t)b;
       d.dcnt[a] = (int16_t)dc;
-      return;
+      done = true;
     }
   }
 }
 
-// Descriptor and changed feature rows (3 per proposal) of proposals
-// i0 .. i0 + cnt - 1, one thread each.
-__global__ __launch_bounds__(256) void k_scr_rows(InstParams P, SurDev S, ScreenDev T, uint64_t seed,
-                                                  uint32_t inst_index, uint32_t i0, uint32_t cnt) {
-  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
-  stage(lds, P.image, P.lay.total_words);
-  __syncthreads();
-  const View V = make_view(lds, P.lay, P.dist);
-  const uint32_t it = P.st->it;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
-    const Move m = decode_move(draw_move(seed, i0 + j, it, inst_index, V, P), V, P);
-    ScreenDesc d;
-    for (int k = 0; k < 3; ++k) d.f[k] = d.bold[k] = d.bnew[k] = 0xFFFF;
-    for (int k = 0; k < 4; ++k) {
-      d.ab[k] = 0xFFFF;
-      d.dcnt[k] = 0;
+// A descriptor as 15 words (for the exchange between lanes) and back.
+constexpr int kDescWords = 15;
+__device__ __forceinline__ uint32_t pk16(uint32_t lo, uint32_t hi) { return (lo & 0xFFFFu) | (hi << 16); }
+__device__ __forceinline__ void desc_pack(const ScreenDesc &d, uint32_t w[kDescWords]) {
+  w[0] = pk16(d.f[0], d.f[1]);
+  w[1] = pk16(d.f[2], d.bold[0]);
+  w[2] = pk16(d.bold[1], d.bold[2]);
+  w[3] = pk16(d.bnew[0], d.bnew[1]);
+  w[4] = pk16(d.bnew[2], d.ab[0]);
+  w[5] = pk16(d.ab[1], d.ab[2]);
+  w[6] = pk16(d.ab[3], d.moved_bp);
+  w[7] = pk16((uint16_t)d.dcnt[0], (uint16_t)d.dcnt[1]);
+  w[8] = pk16((uint16_t)d.dcnt[2], (uint16_t)d.dcnt[3]);
+  w[9] = pk16(d.tg[0], d.tg[1]);
+  w[10] = pk16((uint16_t)d.dnf[0], (uint16_t)d.dnf[1]);
+  w[11] = pk16((uint16_t)d.dnb[0], (uint16_t)d.dnb[1]);
+  w[12] = __float_as_uint(d.u6[0]);
+  w[13] = __float_as_uint(d.u6[1]);
+  w[14] = pk16(d.dst_tour, d.feasible);
+}
+__device__ __forceinline__ void desc_unpack(const uint32_t w[kDescWords], ScreenDesc &d) {
+  auto lo = [](uint32_t x) { return (uint16_t)(x & 0xFFFFu); };
+  auto hi = [](uint32_t x) { return (uint16_t)(x >> 16); };
+  d.f[0] = lo(w[0]);
+  d.f[1] = hi(w[0]);
+  d.f[2] = lo(w[1]);
+  d.bold[0] = hi(w[1]);
+  d.bold[1] = lo(w[2]);
+  d.bold[2] = hi(w[2]);
+  d.bnew[0] = lo(w[3]);
+  d.bnew[1] = hi(w[3]);
+  d.bnew[2] = lo(w[4]);
+  d.ab[0] = hi(w[4]);
+  d.ab[1] = lo(w[5]);
+  d.ab[2] = hi(w[5]);
+  d.ab[3] = lo(w[6]);
+  d.moved_bp = hi(w[6]);
+  d.dcnt[0] = (int16_t)lo(w[7]);
+  d.dcnt[1] = (int16_t)hi(w[7]);
+  d.dcnt[2] = (int16_t)lo(w[8]);
+  d.dcnt[3] = (int16_t)hi(w[8]);
+  d.tg[0] = lo(w[9]);
+  d.tg[1] = hi(w[9]);
+  d.dnf[0] = (int16_t)lo(w[10]);
+  d.dnf[1] = (int16_t)hi(w[10]);
+  d.dnb[0] = (int16_t)lo(w[11]);
+  d.dnb[1] = (int16_t)hi(w[11]);
+  d.u6[0] = __uint_as_float(w[12]);
+  d.u6[1] = __uint_as_float(w[13]);
+  d.dst_tour = lo(w[14]);
+  d.feasible = (uint8_t)hi(w[14]);
+}
+
+// What move m changes relative to the base: its descriptor, and per changed
+// feature row k the field rf[k] (-1: none), its BP rb[k] and its route
+// predecessor rp[k].  The rows are the moved run's first field, the field
+// after the insertion point and the field after the gap it leaves.
+__device__ __forceinline__ void describe(const View &V, const SurDev &S, const ScreenDev &T,
+                                         const Move &m, ScreenDesc &d, int rf[3], int rb[3],
+                                         int rp[3]) {
+  for (int k = 0; k < 3; ++k) {
+    d.f[k] = d.bold[k] = d.bnew[k] = 0xFFFF;
+    rf[k] = -1;
+    rb[k] = 0;
+    rp[k] = -1;
+  }
+  for (int k = 0; k < 4; ++k) {
+    d.ab[k] = 0xFFFF;
+    d.dcnt[k] = 0;
+  }
+  d.tg[0] = d.tg[1] = 0xFFFF;
+  d.dnf[0] = d.dnf[1] = d.dnb[0] = d.dnb[1] = 0;
+  d.u6[0] = d.u6[1] = 0.f;
+  d.moved_bp = d.dst_tour = 0xFFFF;
+  d.feasible = 1;
+  for (int k = 0; k < 5; ++k) d.pad[k] = 0;
+  int Ts, Td, newlast_d = -2, newlast_s = -2;  // -2: unchanged, -1: tour empty
+  const Nbrs nb = move_nbrs(V, m);
+  int b0;
+  if (m.kind == 0) {
+    const int f = m.v, bs = m.src, bd = m.dst;
+    Ts = V.bp_tour[bs];
+    Td = V.bp_tour[bd];
+    if (bs != bd && V.b_sup[bs] - V.supply[f] < V.demand[bs]) d.feasible = 0;
+    add_bp(d, bs, bs == bd ? 0 : -1);
+    add_bp(d, bd, bs == bd ? 0 : 1);
+    if (Ts != Td) {
+      d.dnf[0] = -1;
+      d.dnf[1] = 1;
     }
-    d.tg[0] = d.tg[1] = 0xFFFF;
-    d.dnf[0] = d.dnf[1] = d.dnb[0] = d.dnb[1] = 0;
-    d.u6[0] = d.u6[1] = 0.f;
-    d.moved_bp = d.dst_tour = 0xFFFF;
-    d.feasible = 1;
-    for (int k = 0; k < 5; ++k) d.pad[k] = 0;
-    int rf[3] = {-1, -1, -1}, rb[3] = {0, 0, 0}, rp[3] = {-1, -1, -1};
-    int Ts, Td, newlast_d = -2, newlast_s = -2;  // -2: unchanged, -1: tour empty
-    const Nbrs nb = move_nbrs(V, m);
-    int b0;
-    if (m.kind == 0) {
-      const int f = m.v, bs = m.src, bd = m.dst;
-      Ts = V.bp_tour[bs];
-      Td = V.bp_tour[bd];
-      if (bs != bd && V.b_sup[bs] - V.supply[f] < V.demand[bs]) d.feasible = 0;
-      add_bp(d, bs, bs == bd ? 0 : -1);
-      add_bp(d, bd, bs == bd ? 0 : 1);
-      if (Ts != Td) {
-        d.dnf[0] = -1;
-        d.dnf[1] = 1;
-      }
-      b0 = bd;
-      d.bold[0] = (uint16_t)bs;
-    } else {
-      const int b = m.v, len = V.bp_len[b];
-      Ts = m.src;
-      Td = m.dst;
-      d.moved_bp = (uint16_t)b;
-      d.dst_tour = (uint16_t)Td;
-      add_bp(d, b, 0);
-      if (Ts != Td) {
-        d.dnf[0] = (int16_t)-len;
-        d.dnf[1] = (int16_t)len;
-        d.dnb[0] = -1;
-        d.dnb[1] = 1;
-      }
-      b0 = b;
-      if (len > 0) d.bold[0] = (uint16_t)b;
+    b0 = bd;
+    d.bold[0] = (uint16_t)bs;
+  } else {
+    const int b = m.v, len = V.bp_len[b];
+    Ts = m.src;
+    Td = m.dst;
+    d.moved_bp = (uint16_t)b;
+    d.dst_tour = (uint16_t)Td;
+    add_bp(d, b, 0);
+    if (Ts != Td) {
+      d.dnf[0] = (int16_t)-len;
+      d.dnf[1] = (int16_t)len;
+      d.dnb[0] = -1;
+      d.dnb[1] = 1;
     }
-    // Rows whose route predecessor or BP changes: the moved run's first
-    // field, the field after the insertion point and the one after the gap.
-    if (nb.first >= 0) {
-      rf[0] = nb.first;
-      rb[0] = b0;
-      rp[0] = nb.pnew;
-      if (nb.nnew >= 0) {
-        rf[1] = nb.nnew;
-        rb[1] = V.fbp[nb.nnew];
-        rp[1] = nb.last;
-        d.bold[1] = (uint16_t)rb[1];
-      }
-      if (nb.nold >= 0 && nb.nold != nb.nnew) {
-        rf[2] = nb.nold;
-        rb[2] = V.fbp[nb.nold];
-        rp[2] = nb.pold;
-        d.bold[2] = (uint16_t)rb[2];
-      }
-      if (nb.nnew < 0) newlast_d = nb.last;
-      if (nb.nold < 0) newlast_s = nb.pold;
+    b0 = b;
+    if (len > 0) d.bold[0] = (uint16_t)b;
+  }
+  if (nb.first >= 0) {
+    rf[0] = nb.first;
+    rb[0] = b0;
+    rp[0] = nb.pnew;
+    if (nb.nnew >= 0) {
+      rf[1] = nb.nnew;
+      rb[1] = V.fbp[nb.nnew];
+      rp[1] = nb.last;
+      d.bold[1] = (uint16_t)rb[1];
     }
+    if (nb.nold >= 0 && nb.nold != nb.nnew) {
+      rf[2] = nb.nold;
+      rb[2] = V.fbp[nb.nold];
+      rp[2] = nb.pold;
+      d.bold[2] = (uint16_t)rb[2];
+    }
+    if (nb.nnew < 0) newlast_d = nb.last;
+    if (nb.nold < 0) newlast_s = nb.pold;
+  }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      uint16_t *row = T.phi + ((size_t)j * 3 + k) * kSurK1;
-      if (rf[k] >= 0) {
-        d.f[k] = (uint16_t)rf[k];
-        d.bnew[k] = (uint16_t)rb[k];
-        add_bp(d, rb[k], 0);
-        add_bp(d, d.bold[k], 0);
-        feature_row(V, P, S, row, rf[k], rb[k], rp[k]);
-      } else {
-        float z[16] = {0.f};
-        write_row(row, z);
-      }
-    }
-    // Affected tours and their new return legs.
-    auto last_feat = [&](int g, int nl) -> float {
-      if (nl == -2) return T.ub6[g];
-      return nl >= 0 ? (float)V.dhq[nl] * S.inv_ds : 0.f;
-    };
-    if (Ts == Td) {
-      d.tg[0] = (uint16_t)Ts;
-      d.dnf[0] = 0;
-      d.dnb[0] = 0;
-      d.u6[0] = last_feat(Ts, newlast_d != -2 ? newlast_d : newlast_s);
-    } else {
-      d.tg[0] = (uint16_t)Ts;
-      d.tg[1] = (uint16_t)Td;
-      d.u6[0] = last_feat(Ts, newlast_s);
-      d.u6[1] = last_feat(Td, newlast_d);
-    }
-    T.desc[j] = d;
+  for (int k = 0; k < 3; ++k) {
+    if (rf[k] < 0) continue;
+    d.f[k] = (uint16_t)rf[k];
+    d.bnew[k] = (uint16_t)rb[k];
+    add_bp(d, rb[k], 0);
+    add_bp(d, d.bold[k], 0);
+  }
+  // Affected tours and their new return legs.
+  auto last_feat = [&](int g, int nl) -> float {
+    if (nl == -2) return T.ub6[g];
+    return nl >= 0 ? (float)V.dhq[nl] * S.inv_ds : 0.f;
+  };
+  if (Ts == Td) {
+    d.tg[0] = (uint16_t)Ts;
+    d.dnf[0] = 0;
+    d.dnb[0] = 0;
+    d.u6[0] = last_feat(Ts, newlast_d != -2 ? newlast_d : newlast_s);
+  } else {
+    d.tg[0] = (uint16_t)Ts;
+    d.tg[1] = (uint16_t)Td;
+    d.u6[0] = last_feat(Ts, newlast_s);
+    d.u6[1] = last_feat(Td, newlast_d);
   }
 }
 
-// Predicted (path, makespan) of proposals i0 .. i0+cnt-1 from their
-// descriptors and projected rows; writes their score keys (predicted path,
-// or discarded when infeasible or above the makespan gate).  One wave per
-// proposal, lane c = embedding column c: every row read is one coalesced
-// 256-byte line.
-__global__ __launch_bounds__(256) void k_scr_score(InstParams P, SurDev S, ScreenDev T, uint32_t i0,
-                                                   uint32_t cnt, float mk_margin) {
-  const View V = make_view(P.image, P.lay, P.dist);
-  const int c = threadIdx.x & 63;
+// LDS of the fused screen kernel (byte offsets): bf16 weight operands, the
+// base tables, the instance image, then per wave the changed feature rows of
+// its 64 proposals.
+constexpr uint32_t kFuseW1 = 0;
+constexpr uint32_t kFuseW2 = kFuseW1 + 128 * kLd1 * 2;
+constexpr uint32_t kFuseW3 = kFuseW2 + 128 * kLd2 * 2;
+constexpr uint32_t kFuseB1 = kFuseW3 + 64 * kLd2 * 2;
+constexpr uint32_t kFuseB2 = kFuseB1 + 128 * 4;
+constexpr uint32_t kFuseTab = kFuseB2 + 128 * 4;
+constexpr uint32_t kFuseWaveBytes = 3 * 64 * 32;   // 3 rows of 16 bf16 per proposal
+constexpr int kFuseMaxWaves = 8;
+constexpr int kTabLd = kSurA + 4;   // row stride (floats) of the LDS tables: rows read together
+                                    // by different lanes start in different banks
+constexpr uint32_t kFuseLdsMax = 160 * 1024;
+
+struct FuseLayout {
+  uint32_t q, r, u, cst, yb, ub6, nbg, nfg, scal, topg;  // word offsets in the table area
+  uint32_t img, rows, total;                              // byte offsets
+};
+
+__host__ __device__ inline FuseLayout fuse_layout(int NB, int NT, uint32_t img_words, int waves) {
+  FuseLayout L;
+  L.q = 0;
+  L.r = L.q + NB * kTabLd;
+  L.u = L.r + NT * kTabLd;
+  L.cst = L.u + NT * kTabLd;     // 5 rows: W3 rows of the field and BP counts (pre-divided),
+                                 // of the return leg, and the two head columns
+  L.yb = L.cst + 5 * kTabLd;
+  L.ub6 = L.yb + 2 * NT;
+  L.nbg = L.ub6 + NT;
+  L.nfg = L.nbg + NT;
+  L.scal = L.nfg + NT;
+  L.topg = L.scal + 4;
+  const uint32_t tab_words = L.topg + 4;
+  L.img = kFuseTab + ((tab_words * 4 + 15u) & ~15u);
+  L.rows = L.img + ((img_words * 4 + 15u) & ~15u);
+  L.total = L.rows + (uint32_t)waves * kFuseWaveBytes;
+  return L;
+}
+
+// Two floats rounded to bf16 (round to nearest even), then ReLU on the
+// packed halves as signed 16-bit integers (a negative bf16 has its sign bit
+// set; rounding keeps signs, so this equals rounding after the ReLU).
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef short i16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);
+  const i16x2 m = __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), (i16x2){0, 0});
+  return __builtin_bit_cast(uint32_t, m);
+}
+__device__ __forceinline__ bf16x8 pack8(const uint32_t w[4]) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = {w[0], w[1], w[2], w[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
+  return float4{fmaf(a, x.x, y.x), fmaf(a, x.y, y.y), fmaf(a, x.z, y.z), fmaf(a, x.w, y.w)};
+}
+__device__ __forceinline__ float4 relu4(float4 x) {
+  return float4{fmaxf(x.x, 0.f), fmaxf(x.y, 0.f), fmaxf(x.z, 0.f), fmaxf(x.w, 0.f)};
+}
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+  return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
+}
+
+// Screen of proposals i0 .. i0 + cnt - 1, fused: one wave takes 64 proposals
+// at a time.  Each lane draws one proposal and builds its descriptor and its
+// (up to three) changed feature rows; then, 16 proposals at a time, the MLP
+// runs on bf16 MFMA with the weights as the A operand and the rows as the B
+// operand (the product transposed), so that a layer's fp32 outputs, after
+// bias, ReLU and rounding to bf16, are already the next layer's B operand in
+// registers: the K order inside each 32-wide slab is permuted to match the
+// output layout, in the weights staged to LDS.  Lane l then holds columns
+// 16 mt + 4 (l / 16) + i (mt, i < 4) of the projected rows of proposal l % 16
+// of the group, and the four lanes of a proposal update the base's BP means,
+// tour inputs and head outputs for those columns and add them up.
+__global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, ScreenDev T,
+                                                      uint64_t seed, uint32_t inst_index,
+                                                      uint32_t i0, uint32_t cnt, float mk_margin) {
+  uint8_t *lds = reinterpret_cast<uint8_t *>(g_lds4);
+  const int NB = P.NB, NT = P.NT;
+  const int nwaves = blockDim.x >> 6;
+  const FuseLayout L = fuse_layout(NB, NT, P.lay.total_words, nwaves);
+  uint16_t *w1 = reinterpret_cast<uint16_t *>(lds + kFuseW1);
+  uint16_t *w2 = reinterpret_cast<uint16_t *>(lds + kFuseW2);
+  uint16_t *w3 = reinterpret_cast<uint16_t *>(lds + kFuseW3);
+  float *b1 = reinterpret_cast<float *>(lds + kFuseB1);
+  float *b2 = reinterpret_cast<float *>(lds + kFuseB2);
+  float *tab = reinterpret_cast<float *>(lds + kFuseTab);
+  uint32_t *img = reinterpret_cast<uint32_t *>(lds + L.img);
+  // Staging.  Within slab ks of 32 inputs, position 8 q + j holds input
+  // 32 ks + 4 q + j (j < 4) or 32 ks + 16 + 4 q + j - 4 (j >= 4).
+  for (int i = threadIdx.x; i < 128 * kLd1; i += blockDim.x) w1[i] = S.w1t[i];
+  for (int i = threadIdx.x; i < 128 * 128; i += blockDim.x) {
+    const int m = i >> 7, kk = i & 127, ks = kk >> 5, q = (kk >> 3) & 3, j = kk & 7;
+    const int src = 32 * ks + (j < 4 ? 4 * q + j : 16 + 4 * q + j - 4);
+    w2[m * kLd2 + kk] = S.w2t[m * kLd2 + src];
+    if (m < 64) w3[m * kLd2 + kk] = S.w3et[m * kLd2 + src];
+  }
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    b1[i] = S.W[kSurOffB1 + i];
+    b2[i] = S.W[kSurOffB2 + i];
+  }
+  for (int i = threadIdx.x; i < NB * kSurA; i += blockDim.x) tab[L.q + (i >> 6) * kTabLd + (i & 63)] = T.Q[i];
+  for (int i = threadIdx.x; i < NT * kSurA; i += blockDim.x) {
+    tab[L.r + (i >> 6) * kTabLd + (i & 63)] = T.R[i];
+    tab[L.u + (i >> 6) * kTabLd + (i & 63)] = T.U[i];
+  }
+  for (int c = threadIdx.x; c < kSurA; c += blockDim.x) {
+    tab[L.cst + c] = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c] / (float)P.NF;
+    tab[L.cst + kTabLd + c] = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c] / (float)P.NB;
+    tab[L.cst + 2 * kTabLd + c] = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
+    tab[L.cst + 3 * kTabLd + c] = S.W[kSurOffW4 + 2 * c];
+    tab[L.cst + 4 * kTabLd + c] = S.W[kSurOffW4 + 2 * c + 1];
+  }
+  for (int g = threadIdx.x; g < NT; g += blockDim.x) {
+    tab[L.yb + 2 * g] = T.yb[2 * g];
+    tab[L.yb + 2 * g + 1] = T.yb[2 * g + 1];
+    tab[L.ub6 + g] = T.ub6[g];
+    tab[L.nbg + g] = (float)T.nbg[g];
+    tab[L.nfg + g] = (float)T.nfg[g];
+  }
+  if (threadIdx.x < 4) tab[L.scal + threadIdx.x] = T.scal[threadIdx.x];
+  if (threadIdx.x < 3) tab[L.topg + threadIdx.x] = (float)T.top_g[threadIdx.x];
+  stage(img, P.image, P.lay.total_words);
+  __syncthreads();
+  const View V = make_view(img, P.lay, P.dist);
+  const uint32_t it = P.st->it;
   const float gate = (float)P.st->t_best * S.inv_t0 + mk_margin;
   const float b40 = S.W[kSurOffB4], b41 = S.W[kSurOffB4 + 1];
-  const float w3u4 = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c] / (float)P.NF;
-  const float w3u5 = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c] / (float)P.NB;
-  const float w3u6 = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
-  const float w40 = S.W[kSurOffW4 + 2 * c], w41 = S.W[kSurOffW4 + 2 * c + 1];
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t j = wave; j < cnt; j += nwave) {
-    const ScreenDesc d = T.desc[j];
-    uint32_t key = 0xFFFFFFFFu;
-    if (d.feasible) {
-      // BP means before and after, column c.
-      float eo[4], en[4];
-      int bt[4], ct[4];
-      const float *pr = T.P + (size_t)j * 3 * kSurA;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  // Feature rows: [row k][half][proposal][4 words] (each half holds 8 bf16).
+  uint32_t *rows = reinterpret_cast<uint32_t *>(lds + L.rows + wave * kFuseWaveBytes);
+  const uint32_t ntask = (cnt + 63) / 64;
+  for (uint32_t task = blockIdx.x * nwaves + wave; task < ntask; task += gridDim.x * nwaves) {
+    // Phase 1: one proposal per lane.
+    uint32_t own[kDescWords];
+    {
+      const uint32_t j = task * 64 + lane;
+      int rf[3] = {-1, -1, -1}, rb[3] = {0, 0, 0}, rp[3] = {-1, -1, -1};
+      ScreenDesc dd;
+      if (j < cnt) {
+        const Move m = decode_move(draw_move(seed, i0 + j, it, inst_index, V, P), V, P);
+        describe(V, S, T, m, dd, rf, rb, rp);
+        desc_pack(dd, own);
+      } else {
+        for (int w = 0; w < kDescWords; ++w) own[w] = 0;   // infeasible: no key is written
+      }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        eo[a] = en[a] = 0.f;
-        bt[a] = ct[a] = -1;
-        const int b = d.ab[a];
-        if (b == 0xFFFF) continue;
-        bt[a] = V.bp_tour[b];
-        ct[a] = b == d.moved_bp ? d.dst_tour : bt[a];
-        const int cb = V.bp_len[b], cn = cb + d.dcnt[a];
-        const float qo = T.Q[b * kSurA + c];
-        float qn = qo;
+      for (int k = 0; k < 3; ++k) {
+        uint32_t pk[8];
+        if (rf[k] >= 0) {
+          float v[16];
+          feature_vals(V, P, S, rf[k], rb[k], rp[k], v);
+          for (int x = 0; x < 8; ++x) pk[x] = (uint32_t)to_bf16(v[2 * x]) | ((uint32_t)to_bf16(v[2 * x + 1]) << 16);
+        } else {
+          for (int x = 0; x < 8; ++x) pk[x] = 0u;
+        }
+        *reinterpret_cast<uint4 *>(rows + ((2 * k) * 64 + lane) * 4) = uint4{pk[0], pk[1], pk[2], pk[3]};
+        *reinterpret_cast<uint4 *>(rows + ((2 * k + 1) * 64 + lane) * 4) = uint4{pk[4], pk[5], pk[6], pk[7]};
+      }
+    }
+    wave_sync();
+    // Phase 2: 16 proposals at a time.
+#pragma unroll 1
+    for (int grp = 0; grp < 4; ++grp) {
+      // Keeps the weight operands from being hoisted out of the loop into
+      // registers (they are re-read from LDS for every group).
+      __asm__ volatile("" ::: "memory");
+      const int p = 16 * grp + r;
+      // The descriptor of proposal p.
+      ScreenDesc d;
+      {
+        uint32_t ew[kDescWords];
+#pragma unroll
+        for (int w = 0; w < kDescWords; ++w) ew[w] = (uint32_t)__shfl((int)own[w], p, 64);
+        desc_unpack(ew, d);
+      }
+      // Base rows of the changed fields (global memory: issued before the MLP).
+      int prow[3];
+      float4 pb[3][4];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        prow[k] = d.f[k] != 0xFFFF ? V.pos[d.f[k]] : 0;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+          pb[k][mt] = *reinterpret_cast<const float4 *>(S.P + (size_t)prow[k] * kSurA + 16 * mt + 4 * q);
+      }
+      // Layer 1: 16 (padded to 32) -> 128, bias (as the accumulator's start),
+      // ReLU.  All 24 products are issued before the first result is used.
+      bf16x8 h1[3][4];
+      {
+        bf16x8 x[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x[k] = q < 2 ? ld8(reinterpret_cast<const uint16_t *>(rows + ((2 * k + q) * 64 + p) * 4)) : zero8();
+        floatx4 acc[3][8];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+          const bf16x8 a = ld8(w1 + (nt * 16 + r) * kLd1 + 8 * q);
+          const floatx4 bb = *reinterpret_cast<const floatx4 *>(b1 + nt * 16 + 4 * q);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc[k][nt] = mfma(a, x[k], bb);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const uint32_t w[4] = {relu_bf16x2(acc[k][2 * ks][0], acc[k][2 * ks][1]),
+                                   relu_bf16x2(acc[k][2 * ks][2], acc[k][2 * ks][3]),
+                                   relu_bf16x2(acc[k][2 * ks + 1][0], acc[k][2 * ks + 1][1]),
+                                   relu_bf16x2(acc[k][2 * ks + 1][2], acc[k][2 * ks + 1][3])};
+            h1[k][ks] = pack8(w);
+          }
+      }
+      // Layer 2: 128 -> 128, bias, ReLU; output tiles in pairs (six
+      // independent accumulation chains).
+      bf16x8 h2[3][4];
+#pragma unroll
+      for (int mp = 0; mp < 4; ++mp) {
+        floatx4 acc[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const floatx4 bb = *reinterpret_cast<const floatx4 *>(b2 + (2 * mp + h) * 16 + 4 * q);
+          acc[h][0] = acc[h][1] = acc[h][2] = bb;
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const bf16x8 a = ld8(w2 + ((2 * mp + h) * 16 + r) * kLd2 + 32 * ks + 8 * q);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[h][k] = mfma(a, h1[k][ks], acc[h][k]);
+          }
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          if (d.f[k] == 0xFFFF) continue;
-          if (d.bold[k] == b) qn -= S.P[(size_t)V.pos[d.f[k]] * kSurA + c];
-          if (d.bnew[k] == b) qn += pr[k * kSurA + c];
+          const uint32_t w[4] = {relu_bf16x2(acc[0][k][0], acc[0][k][1]), relu_bf16x2(acc[0][k][2], acc[0][k][3]),
+                                 relu_bf16x2(acc[1][k][0], acc[1][k][1]), relu_bf16x2(acc[1][k][2], acc[1][k][3])};
+          h2[k][mp] = pack8(w);
         }
-        eo[a] = cb > 0 ? qo / (float)cb : 0.f;
-        en[a] = cn > 0 ? qn / (float)cn : 0.f;
       }
-      float y0[2] = {0.f, 0.f}, y1[2] = {0.f, 0.f};
+      // Layer 3: the pooled-embedding rows of W3, 128 -> 64, no bias (twelve
+      // independent chains).
+      floatx4 pn[3][4];
 #pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        if (d.tg[tt] == 0xFFFF) continue;
-        const int g = d.tg[tt];
-        float R = T.R[g * kSurA + c];
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pn[k][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const bf16x8 a = ld8(w3 + (mt * 16 + r) * kLd2 + 32 * ks + 8 * q);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pn[k][mt] = mfma(a, h2[k][ks], pn[k][mt]);
+        }
+      // Per-lane coefficients: tour tt's summed BP means change by
+      // sum_a cq[tt][a] Q[b_a] + sum_k cn[tt][k] Pnew_k - sum_k cb[tt][k] Pbase_k.
+      const int g0 = d.tg[0] == 0xFFFF ? 0 : d.tg[0];
+      const bool has1 = d.tg[1] != 0xFFFF;
+      const int g1 = has1 ? d.tg[1] : g0;
+      float cq[2][4], en[2][4];
+      int qrow[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int b = d.ab[a];
+        const bool ok = b != 0xFFFF;
+        const int bb = ok ? b : 0;
+        qrow[a] = bb;
+        const int bt = V.bp_tour[bb];
+        const int ct = bb == d.moved_bp ? d.dst_tour : bt;
+        const int cb = V.bp_len[bb], cn = cb + d.dcnt[a];
+        const float io = ok && cb > 0 ? 1.f / (float)cb : 0.f;
+        const float in = ok && cn > 0 ? 1.f / (float)cn : 0.f;
+        en[0][a] = ct == g0 ? in : 0.f;
+        en[1][a] = has1 && ct == g1 ? in : 0.f;
+        cq[0][a] = en[0][a] - (bt == g0 ? io : 0.f);
+        cq[1][a] = en[1][a] - (has1 && bt == g1 ? io : 0.f);
+      }
+      float cn_[2][3], cb_[2][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const bool fv = d.f[k] != 0xFFFF;
+        cn_[0][k] = cn_[1][k] = cb_[0][k] = cb_[1][k] = 0.f;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          if (bt[a] == g) R -= eo[a];
-          if (ct[a] == g) R += en[a];
+          if (fv && d.ab[a] != 0xFFFF && d.bnew[k] == d.ab[a]) {
+            cn_[0][k] += en[0][a];
+            cn_[1][k] += en[1][a];
+          }
+          if (fv && d.ab[a] != 0xFFFF && d.bold[k] == d.ab[a]) {
+            cb_[0][k] += en[0][a];
+            cb_[1][k] += en[1][a];
+          }
         }
-        const int nbn = T.nbg[g] + d.dnb[tt];
-        const float z = (nbn > 0 ? R / (float)nbn : 0.f) + T.U[g * kSurA + c] + (float)d.dnf[tt] * w3u4 +
-                        (float)d.dnb[tt] * w3u5 + (d.u6[tt] - T.ub6[g]) * w3u6;
-        const float act = fmaxf(z, 0.f);
-        y0[tt] = wave_sum(act * w40) + b40;
-        y1[tt] = wave_sum(act * w41) + b41;
       }
-      float pp = T.scal[0];
+      const int nb0 = (int)tab[L.nbg + g0] + d.dnb[0], nb1_ = (int)tab[L.nbg + g1] + d.dnb[1];
+      const float i0n = nb0 > 0 ? 1.f / (float)nb0 : 0.f, i1n = nb1_ > 0 ? 1.f / (float)nb1_ : 0.f;
+      const float du0 = d.u6[0] - tab[L.ub6 + g0], du1 = d.u6[1] - tab[L.ub6 + g1];
+      const float f0 = (float)d.dnf[0], f1 = (float)d.dnf[1];
+      const float e0 = (float)d.dnb[0], e1 = (float)d.dnb[1];
+      float y00 = 0.f, y01 = 0.f, y10 = 0.f, y11 = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        // Bounds the loads in flight to one 4-column slice.
+        __asm__ volatile("" ::: "memory");
+        const int co = 16 * mt + 4 * q;
+        float4 s0 = *reinterpret_cast<const float4 *>(tab + L.r + g0 * kTabLd + co);
+        float4 s1 = *reinterpret_cast<const float4 *>(tab + L.r + g1 * kTabLd + co);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float4 t = *reinterpret_cast<const float4 *>(tab + L.q + qrow[a] * kTabLd + co);
+          s0 = fma4(cq[0][a], t, s0);
+          s1 = fma4(cq[1][a], t, s1);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float4 pnk = {pn[k][mt][0], pn[k][mt][1], pn[k][mt][2], pn[k][mt][3]};
+          s0 = fma4(cn_[0][k], pnk, fma4(-cb_[0][k], pb[k][mt], s0));
+          s1 = fma4(cn_[1][k], pnk, fma4(-cb_[1][k], pb[k][mt], s1));
+        }
+        const float4 u0 = *reinterpret_cast<const float4 *>(tab + L.u + g0 * kTabLd + co);
+        const float4 u1 = *reinterpret_cast<const float4 *>(tab + L.u + g1 * kTabLd + co);
+        const float4 c4 = *reinterpret_cast<const float4 *>(tab + L.cst + co);
+        const float4 c5 = *reinterpret_cast<const float4 *>(tab + L.cst + kTabLd + co);
+        const float4 c6 = *reinterpret_cast<const float4 *>(tab + L.cst + 2 * kTabLd + co);
+        const float4 v0 = *reinterpret_cast<const float4 *>(tab + L.cst + 3 * kTabLd + co);
+        const float4 v1 = *reinterpret_cast<const float4 *>(tab + L.cst + 4 * kTabLd + co);
+        const float4 z0 = s0 * i0n + u0 + f0 * c4 + e0 * c5 + du0 * c6;
+        const float4 z1 = s1 * i1n + u1 + f1 * c4 + e1 * c5 + du1 * c6;
+        const float4 a0 = relu4(z0), a1 = relu4(z1);
+        y00 += dot4(a0, v0);
+        y01 += dot4(a0, v1);
+        y10 += dot4(a1, v0);
+        y11 += dot4(a1, v1);
+      }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        y00 += __shfl_xor(y00, off, 64);
+        y01 += __shfl_xor(y01, off, 64);
+        y10 += __shfl_xor(y10, off, 64);
+        y11 += __shfl_xor(y11, off, 64);
+      }
+      // Predicted path and makespan from the base's.
+      float pp = tab[L.scal];
       float mm = -__builtin_inff();
       for (int k = 0; k < 3; ++k) {
-        const int g = T.top_g[k];
+        const int g = (int)tab[L.topg + k];
         if (g >= 0 && g != d.tg[0] && g != d.tg[1]) {
-          mm = T.scal[1 + k];
+          mm = tab[L.scal + 1 + k];
           break;
         }
       }
-      for (int tt = 0; tt < 2; ++tt) {
-        if (d.tg[tt] == 0xFFFF) continue;
-        const int g = d.tg[tt];
-        if (T.nfg[g] > 0) pp -= T.yb[2 * g];
-        if (T.nfg[g] + d.dnf[tt] > 0) {
-          pp += y0[tt];
-          mm = fmaxf(mm, y1[tt]);
+      {
+        const int nf = (int)tab[L.nfg + g0];
+        if (nf > 0) pp -= tab[L.yb + 2 * g0];
+        if (nf + d.dnf[0] > 0) {
+          pp += y00 + b40;
+          mm = fmaxf(mm, y01 + b41);
         }
       }
-      if (mm <= gate) key = score_key(pp);
+      if (has1) {
+        const int nf = (int)tab[L.nfg + g1];
+        if (nf > 0) pp -= tab[L.yb + 2 * g1];
+        if (nf + d.dnf[1] > 0) {
+          pp += y10 + b40;
+          mm = fmaxf(mm, y11 + b41);
+        }
+      }
+      const uint32_t j = task * 64 + p;
+      if (q == 0 && j < cnt) T.keys[i0 + j] = d.feasible && mm <= gate ? score_key(pp) : 0xFFFFFFFFu;
     }
-    if (c == 0) T.keys[i0 + j] = key;
+    wave_sync();
   }
 }
 
@@ -1137,27 +1481,30 @@ hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float 
 
 size_t sur_head_lds(const InstParams &P) { return (size_t)4 * P.NB * kSurA * 4; }
 
-// Screen n_prop proposals against the base: base forward and tables, then
-// chunks of descriptors + changed rows -> MLP rows -> scores, then the k
-// best-predicted proposal indices into T.short_idx.
+// Waves per workgroup of the fused screen kernel on instance P (0: its
+// tables and image leave no room for one wave in LDS).
+int screen_waves(const InstParams &P) {
+  for (int w = kFuseMaxWaves; w >= 1; --w)
+    if (fuse_layout(P.NB, P.NT, P.lay.total_words, w).total <= kFuseLdsMax) return w;
+  return 0;
+}
+
+// Screen n_prop proposals against the base: base forward and tables, the
+// fused kernel's score keys, then the k best-predicted proposal indices into
+// T.short_idx.
 hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
                          uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
-                         uint32_t chunk, int n_cu, hipStream_t s) {
+                         int n_cu, hipStream_t s) {
+  const int waves = screen_waves(P);
+  if (waves == 0) return hipErrorInvalidValue;
   hipError_t e = launch_sur_forward(P, S, nullptr, 1, 1, false, n_cu, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scr_tables, dim3(1), dim3(1024), 0, s, P, S, T);
-  const size_t lds_img = (size_t)round4(P.lay.total_words) * 4;
-  const size_t lds_fwd = (size_t)(128 * kLd1 + 128 * kLd2 + 64 * kLd2) * 2 + 256 * 4 + 4 * 16 * kLd2 * 2;
-  for (uint32_t i0 = 0; i0 < n_prop; i0 += chunk) {
-    const uint32_t cnt = std::min(chunk, n_prop - i0);
-    const uint32_t gb = std::min<uint32_t>((cnt + 255) / 256, (uint32_t)n_cu * 4);
-    hipLaunchKernelGGL(k_scr_rows, dim3(gb), dim3(256), lds_img, s, P, S, T, seed, inst_index, i0, cnt);
-    const uint32_t rows = 3 * cnt, tiles = (rows + 15) / 16;
-    const uint32_t gf = std::min<uint32_t>((tiles + 3) / 4, (uint32_t)n_cu * 2);
-    hipLaunchKernelGGL(k_sur_fwd, dim3(gf), dim3(256), lds_fwd, s, S, T.phi, rows, T.P, nullptr, nullptr);
-    const uint32_t gs = std::min<uint32_t>((cnt + 3) / 4, (uint32_t)n_cu * 8);
-    hipLaunchKernelGGL(k_scr_score, dim3(gs), dim3(256), 0, s, P, S, T, i0, cnt, mk_margin);
-  }
+  const uint32_t lds = fuse_layout(P.NB, P.NT, P.lay.total_words, waves).total;
+  const uint32_t tasks = (n_prop + 63) / 64;
+  const uint32_t grid = std::min<uint32_t>((tasks + waves - 1) / waves, (uint32_t)n_cu);
+  hipLaunchKernelGGL(k_scr_fused, dim3(grid), dim3(64 * waves), lds, s, P, S, T, seed, inst_index, 0u,
+                     n_prop, mk_margin);
   hipLaunchKernelGGL(k_sur_zero, dim3(8), dim3(256), 0, s, reinterpret_cast<float *>(T.hist), 2048u);
   hipLaunchKernelGGL(k_sur_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(T.sel), 8u);
   for (int pass = 0; pass < 3; ++pass) {
@@ -1200,6 +1547,9 @@ hipError_t sur_setup_attributes() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, fwd);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_sur_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bwd);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_scr_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          kFuseLdsMax);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_sur_head, hipFuncAttributeMaxDynamicSharedMemorySize,
                              160 * 1024);
