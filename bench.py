@@ -216,6 +216,12 @@ def _timed_run(ctx, stream, iid, x0, iters, step):
     return t, c
 
 
+# Algorithmic bf16 FLOP of one screened proposal: three changed field rows,
+# each through 16 -> 128 -> 128 -> 64 (the pooled-embedding rows of W3).
+SCREEN_FLOPS_PER_PROPOSAL = 3 * 2 * (16 * 128 + 128 * 128 + 128 * 64)
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 MFMA
+
+
 def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pairs=1 << 22,
                       per_base=1 << 16, max_examples=1024, mk_margin=0.05, err_threshold=0.1,
                       n_control=1 << 12):
@@ -270,37 +276,58 @@ def screen_comparison(iters=300, n_plain=1 << 22, n_prop=1 << 24, k=1 << 18, pai
     lv = d_loss.cpu().numpy()
     loss = float(lv[0] / max(lv[1], 1.0))
 
-    # Screened search (one eager call first sizes the screen's buffers).
-    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
-    ctx.search_start(iid, 1)
-    ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold,
-                        n_control=n_control)
-    s0 = ctx.sur_stats(sur)
-    ts, cs = _timed_run(ctx, stream, iid, x0, iters, lambda: ctx.sur_search_step(
-        sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold,
-        n_control=n_control))
-    s1 = ctx.sur_stats(sur)
-    ctx.close()
+    # Screened search (one eager call first sizes the screen's buffers):
+    # without a control sample (the screen alone) and with one (an exact
+    # sample that joins the argmin and sends the iteration to the plain batch
+    # when it holds an improvement the shortlist misses).
+    def screened(nc):
+        ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+        ctx.search_start(iid, 1)
+        ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin,
+                            err_threshold=err_threshold, n_control=nc)
+        s0 = ctx.sur_stats(sur)
+        ts, cs = _timed_run(ctx, stream, iid, x0, iters, lambda: ctx.sur_search_step(
+            sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin, err_threshold=err_threshold,
+            n_control=nc))
+        s1 = ctx.sur_stats(sur)
+        th, ih = reach(ts, cs)
+        return {"n_control": nc, "best_km": cs[-1] / 1e3, "ms_per_iteration": ts[-1] / iters * 1e3,
+                "time_to_target_s": th, "iterations_to_target": ih,
+                "time_to_target_with_training_s": None if th is None else th + t_train,
+                "fallback_iterations": s1["fallbacks"] - s0["fallbacks"],
+                "last_mean_rel_error": s1["last_error"]}
 
     def reach(t, c):
         hit = np.nonzero(c <= target)[0]
         return (float(t[hit[0]]), int(hit[0]) + 1) if hit.size else (None, None)
+    runs = [screened(0), screened(n_control)]
+    # The scoring kernel alone, timed with HIP events on its stream.
+    ctx.timing_read()
+    ctx.timing_enable(True, bl.TIMING_SCREEN)
+    for _ in range(10):
+        ctx.sur_search_step(sur, seed, thr, n_prop, k, n_plain, mk_margin=mk_margin,
+                            err_threshold=err_threshold, n_control=n_control)
+    scr_ms, scr_n = ctx.timing_read()
+    ctx.timing_enable(False)
+    ctx.close()
+    scr_ms /= max(scr_n, 1)
+    scr_tflops = n_prop * SCREEN_FLOPS_PER_PROPOSAL / (scr_ms * 1e-3) / 1e12
+
     tp_hit, ip_hit = reach(tp, cp)
-    ts_hit, is_hit = reach(ts, cs)
     return {
         "workload": "clust500 instance; plain: %d exact candidates/iteration; screened: %d proposals -> "
-                    "%d exact + %d control (fallback %d); %d iterations each, seed 0, eps 0.5"
+                    "%d exact (+ %d control, fallback %d); %d iterations each, seed 0, eps 0.5"
                     % (n_plain, n_prop, k, n_control, n_plain, iters),
         "target_km": target / 1e3,
         "plain": {"best_km": cp[-1] / 1e3, "ms_per_iteration": tp[-1] / iters * 1e3,
                   "time_to_target_s": tp_hit, "iterations_to_target": ip_hit},
-        "screened": {"best_km": cs[-1] / 1e3, "ms_per_iteration": ts[-1] / iters * 1e3,
-                     "time_to_target_s": ts_hit, "iterations_to_target": is_hit,
-                     "time_to_target_with_training_s": None if ts_hit is None else ts_hit + t_train,
-                     "fallback_iterations": s1["fallbacks"] - s0["fallbacks"],
-                     "last_mean_rel_error": s1["last_error"]},
+        "screened": runs[0],
+        "screened_with_control": runs[1],
         "training": {"pairs": n_bases * per_base, "seconds": t_train, "final_loss": loss,
                      "examples_per_step": max_examples},
+        "roofline": {"kernel": "k_scr_fused", "bound": "mfma", "achieved": scr_tflops,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": scr_tflops / BF16_PEAK_TFLOPS,
+                     "flops_per_proposal": SCREEN_FLOPS_PER_PROPOSAL, "kernel_ms_per_launch": scr_ms},
     }
 
 

@@ -340,8 +340,8 @@ bl_status bl_sur_screen(bl_ctx *ctx, int32_t sur, const bl_search_params *p,
  * bl_sur_screen and a control sample, proposals 0 .. n_control-1, all
  * evaluated exactly.  The exact results also judge the screen: when no
  * shortlisted candidate passes the exact gate, when the control sample's
- * best key is below the shortlist's (the screen did worse than an
- * unscreened sample), or when the scatter of the predicted path around the
+ * best key is below the shortlist's and its cost below x*'s (the screen
+ * missed an improvement that an unscreened sample found), or when the scatter of the predicted path around the
  * exact cost over the shortlisted candidates that have one (standard
  * deviation of predicted - exact, km, divided by the mean exact cost; a
  * common offset does not change the ranking and is not counted) exceeds
@@ -362,12 +362,17 @@ typedef struct {
 /* Counters of bl_sur_search_step.  Synchronising. */
 bl_status bl_sur_stats_get(bl_ctx *ctx, int32_t sur, bl_sur_stats *out);
 
-/* Kernel timing.  While enabled, every launch of the evaluation kernel made
- * by bl_search_step or bl_evaluate_batch is bracketed by two HIP events on
- * the context's stream.  bl_timing_read synchronises, returns the summed
- * kernel time in ms and the number of bracketed launches since the last
- * read, and resets both. */
-bl_status bl_timing_enable(bl_ctx *ctx, int32_t on);
+/* Kernel timing.  what = BL_TIMING_EVAL: every launch of the evaluation
+ * kernel made by bl_search_step, bl_evaluate_batch or bl_batch_step is
+ * bracketed by two HIP events on the context's stream; BL_TIMING_SCREEN:
+ * every launch of the screen's scoring kernel (bl_sur_screen,
+ * bl_sur_search_step); 0: off.  Launches inside a capture are not timed.
+ * bl_timing_read synchronises, returns the summed kernel time in ms and the
+ * number of bracketed launches since the last read, and resets both.
+ * Another value of what: BL_EINVAL. */
+#define BL_TIMING_EVAL 1
+#define BL_TIMING_SCREEN 2
+bl_status bl_timing_enable(bl_ctx *ctx, int32_t what);
 bl_status bl_timing_read(bl_ctx *ctx, double *eval_ms, uint32_t *n_launches);
 
 #ifdef __cplusplus

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(PKG, "libbl.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT, FULL_WALK, WIDE_KEYS = 1, 2, 4, 8, 16, 32
+TIMING_EVAL = 1
+TIMING_SCREEN = 2
 CAND_INFEASIBLE, CAND_GATED, CAND_CAP_HU, CAND_CAP_SU, CAND_INVALID, CAND_INF_MAKESPAN = (
     1, 2, 4, 8, 16, 32)
 SLOT_BASE, SLOT_BEST, SLOT_OLD = 0, 1, 2
@@ -310,11 +312,14 @@ class Context:
         return [dict(best_key=r.best_key, cost_m=r.cost_m, makespan_s=r.makespan_s, it=r.it,
                      indicator=r.indicator, use_best=r.use_best) for r in buf[:got.value]]
 
-    def timing_enable(self, on: bool = True):
-        self._check(self._lib.bl_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, on: bool = True, kind: int = None):
+        """Time launches of the evaluation kernel (kind TIMING_EVAL, the
+        default) or of the screen's scoring kernel (TIMING_SCREEN)."""
+        kind = TIMING_EVAL if kind is None else kind
+        self._check(self._lib.bl_timing_enable(self._h, kind if on else 0))
 
     def timing_read(self):
-        """(summed evaluation-kernel ms, launches) since the last read."""
+        """(summed kernel ms, launches) of the timed kind since the last read."""
         ms, n = C.c_double(), C.c_uint32()
         self._check(self._lib.bl_timing_read(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value

@@ -239,9 +239,12 @@ hipError_t launch_sur_backward(const InstParams &P, const SurDev &S, uint32_t n,
 hipError_t launch_sur_adam(const SurDev &S, float lr, float b1, float b2, float eps, float scale,
                            uint32_t step, hipStream_t s);
 
-hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
-                         uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
-                         int n_cu, hipStream_t s);
+hipError_t launch_screen_base(const InstParams &P, const SurDev &S, const ScreenDev &T, int n_cu,
+                              hipStream_t s);
+hipError_t launch_screen_score(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
+                               uint32_t inst_index, uint32_t n_prop, float mk_margin, int n_cu,
+                               hipStream_t s);
+hipError_t launch_screen_select(const ScreenDev &T, uint32_t n_prop, uint32_t k, hipStream_t s);
 int screen_waves(const InstParams &P);
 hipError_t launch_scr_export(const ScreenDev &T, uint32_t n, float *score, hipStream_t s);
 hipError_t launch_scr_check(const InstParams &P, const SurDev &S, const ScreenDev &T, uint32_t k,

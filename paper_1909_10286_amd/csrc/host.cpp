@@ -82,8 +82,8 @@ struct bl_ctx {
   std::vector<hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;  // private stream used only while capturing
   bool capturing = false;
-  // kernel timing: event pairs recorded around evaluation launches
-  bool timing = false;
+  // kernel timing: event pairs recorded around launches of one kind
+  int timing = 0;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
 };
@@ -197,9 +197,10 @@ bl_status validate_solution(bl_ctx *c, const Instance &I, const bl_solution *s) 
   return BL_OK;
 }
 
-// Records one timing event (when enabled); returns false on a HIP error.
-hipError_t timing_mark(bl_ctx *c) {
-  if (!c->timing || c->capturing) return hipSuccess;
+// Records one timing event when launches of this kind are being timed.
+enum { kTimeEval = BL_TIMING_EVAL, kTimeScreen = BL_TIMING_SCREEN };
+hipError_t timing_mark(bl_ctx *c, int kind = kTimeEval) {
+  if (c->timing != kind || c->capturing) return hipSuccess;
   if (c->events_used == c->events.size()) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
@@ -1351,8 +1352,12 @@ bl_status screen_on(bl_ctx *c, Sur *S, const bl_search_params *p, const bl_scree
   if (st != BL_OK) return st;
   q = work_stream(c);
   HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
-  HIP_TRY(c, launch_screen(I->P, S->D, S->T, p->seed, p->inst_index, sc->n_proposals, sc->n_shortlist,
-                           sc->mk_margin, c->n_cu, q));
+  HIP_TRY(c, launch_screen_base(I->P, S->D, S->T, c->n_cu, q));
+  HIP_TRY(c, timing_mark(c, kTimeScreen));
+  HIP_TRY(c, launch_screen_score(I->P, S->D, S->T, p->seed, p->inst_index, sc->n_proposals, sc->mk_margin,
+                                 c->n_cu, q));
+  HIP_TRY(c, timing_mark(c, kTimeScreen));
+  HIP_TRY(c, launch_screen_select(S->T, sc->n_proposals, sc->n_shortlist, q));
   return BL_OK;
 }
 
@@ -1412,9 +1417,10 @@ bl_status bl_sur_stats_get(bl_ctx *c, int32_t id, bl_sur_stats *out) {
   return BL_OK;
 }
 
-bl_status bl_timing_enable(bl_ctx *c, int32_t on) {
+bl_status bl_timing_enable(bl_ctx *c, int32_t what) {
   if (!c) return BL_EINVAL;
-  c->timing = on != 0;
+  if (what < 0 || what > BL_TIMING_SCREEN) return fail(c, BL_EINVAL, "timing: 0, BL_TIMING_EVAL or BL_TIMING_SCREEN");
+  c->timing = what;
   return BL_OK;
 }
 

@@ -812,20 +812,19 @@ constexpr int kTabLd = kSurA + 4;   // row stride (floats) of the LDS tables: ro
 constexpr uint32_t kFuseLdsMax = 160 * 1024;
 
 struct FuseLayout {
-  uint32_t q, r, u, cst, yb, ub6, nbg, nfg, scal, topg;  // word offsets in the table area
-  uint32_t img, rows, total;                              // byte offsets
+  uint32_t q, rz, cst, yb, nbg, nfg, scal, topg;  // word offsets in the table area
+  uint32_t img, rows, total;                      // byte offsets
 };
 
 __host__ __device__ inline FuseLayout fuse_layout(int NB, int NT, uint32_t img_words, int waves) {
   FuseLayout L;
-  L.q = 0;
-  L.r = L.q + NB * kTabLd;
-  L.u = L.r + NT * kTabLd;
-  L.cst = L.u + NT * kTabLd;     // 5 rows: W3 rows of the field and BP counts (pre-divided),
-                                 // of the return leg, and the two head columns
-  L.yb = L.cst + 5 * kTabLd;
-  L.ub6 = L.yb + 2 * NT;
-  L.nbg = L.ub6 + NT;
+  L.q = 0;                       // [NB] BP sums of the base's projected rows
+  L.rz = L.q + NB * kTabLd;      // [NT][3] head input of each tour before the changes, for a
+                                 // BP count change of -1, 0, +1 (see below)
+  L.cst = L.rz + 3 * NT * kTabLd;  // 4 rows: W3 rows of the field count (pre-divided) and of
+                                   // the return leg, and the two head columns
+  L.yb = L.cst + 4 * kTabLd;
+  L.nbg = L.yb + 2 * NT;
   L.nfg = L.nbg + NT;
   L.scal = L.nfg + NT;
   L.topg = L.scal + 4;
@@ -853,6 +852,7 @@ __device__ __forceinline__ bf16x8 pack8(const uint32_t w[4]) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
   return float4{fmaf(a, x.x, y.x), fmaf(a, x.y, y.y), fmaf(a, x.z, y.z), fmaf(a, x.w, y.w)};
 }
@@ -901,22 +901,27 @@ __global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, Sc
     b1[i] = S.W[kSurOffB1 + i];
     b2[i] = S.W[kSurOffB2 + i];
   }
+  // Head input of tour g, column c, when its BP count changes by e and
+  // nothing else: R/(nb + e) + U + e w3[BP count] / NB - ub6 w3[return leg]
+  // (the proposal adds its own return leg and field count terms).
   for (int i = threadIdx.x; i < NB * kSurA; i += blockDim.x) tab[L.q + (i >> 6) * kTabLd + (i & 63)] = T.Q[i];
-  for (int i = threadIdx.x; i < NT * kSurA; i += blockDim.x) {
-    tab[L.r + (i >> 6) * kTabLd + (i & 63)] = T.R[i];
-    tab[L.u + (i >> 6) * kTabLd + (i & 63)] = T.U[i];
+  for (int i = threadIdx.x; i < 3 * NT * kSurA; i += blockDim.x) {
+    const int g = i / (3 * kSurA), e = (i / kSurA) % 3 - 1, c = i & 63;
+    const int nb = T.nbg[g] + e;
+    const float w5 = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c] / (float)P.NB;
+    const float w6 = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
+    tab[L.rz + (3 * g + e + 1) * kTabLd + c] =
+        (nb > 0 ? T.R[g * kSurA + c] / (float)nb : 0.f) + T.U[g * kSurA + c] + (float)e * w5 - T.ub6[g] * w6;
   }
   for (int c = threadIdx.x; c < kSurA; c += blockDim.x) {
     tab[L.cst + c] = S.W[kSurOffW3 + (kSurH + 4) * kSurA + c] / (float)P.NF;
-    tab[L.cst + kTabLd + c] = S.W[kSurOffW3 + (kSurH + 5) * kSurA + c] / (float)P.NB;
-    tab[L.cst + 2 * kTabLd + c] = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
-    tab[L.cst + 3 * kTabLd + c] = S.W[kSurOffW4 + 2 * c];
-    tab[L.cst + 4 * kTabLd + c] = S.W[kSurOffW4 + 2 * c + 1];
+    tab[L.cst + kTabLd + c] = S.W[kSurOffW3 + (kSurH + 6) * kSurA + c];
+    tab[L.cst + 2 * kTabLd + c] = S.W[kSurOffW4 + 2 * c];
+    tab[L.cst + 3 * kTabLd + c] = S.W[kSurOffW4 + 2 * c + 1];
   }
   for (int g = threadIdx.x; g < NT; g += blockDim.x) {
     tab[L.yb + 2 * g] = T.yb[2 * g];
     tab[L.yb + 2 * g + 1] = T.yb[2 * g + 1];
-    tab[L.ub6 + g] = T.ub6[g];
     tab[L.nbg + g] = (float)T.nbg[g];
     tab[L.nfg + g] = (float)T.nfg[g];
   }
@@ -1055,11 +1060,15 @@ __global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, Sc
 #pragma unroll
           for (int k = 0; k < 3; ++k) pn[k][mt] = mfma(a, h2[k][ks], pn[k][mt]);
         }
-      // Per-lane coefficients: tour tt's summed BP means change by
-      // sum_a cq[tt][a] Q[b_a] + sum_k cn[tt][k] Pnew_k - sum_k cb[tt][k] Pbase_k.
+      // Per-lane coefficients: the head input of tour tt is its table row
+      // plus sum_a cq[tt][a] Q[b_a] + sum_k (cn[tt][k] Pnew_k - cb[tt][k] Pbase_k)
+      // (the changes of its BP means, over its new BP count) plus the field
+      // count and return leg terms.
       const int g0 = d.tg[0] == 0xFFFF ? 0 : d.tg[0];
       const bool has1 = d.tg[1] != 0xFFFF;
       const int g1 = has1 ? d.tg[1] : g0;
+      const int nb0 = (int)tab[L.nbg + g0] + d.dnb[0], nb1_ = (int)tab[L.nbg + g1] + d.dnb[1];
+      const float i0n = nb0 > 0 ? rcp((float)nb0) : 0.f, i1n = nb1_ > 0 ? rcp((float)nb1_) : 0.f;
       float cq[2][4], en[2][4];
       int qrow[4];
 #pragma unroll
@@ -1071,12 +1080,12 @@ __global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, Sc
         const int bt = V.bp_tour[bb];
         const int ct = bb == d.moved_bp ? d.dst_tour : bt;
         const int cb = V.bp_len[bb], cn = cb + d.dcnt[a];
-        const float io = ok && cb > 0 ? 1.f / (float)cb : 0.f;
-        const float in = ok && cn > 0 ? 1.f / (float)cn : 0.f;
-        en[0][a] = ct == g0 ? in : 0.f;
-        en[1][a] = has1 && ct == g1 ? in : 0.f;
-        cq[0][a] = en[0][a] - (bt == g0 ? io : 0.f);
-        cq[1][a] = en[1][a] - (has1 && bt == g1 ? io : 0.f);
+        const float io = ok && cb > 0 ? rcp((float)cb) : 0.f;
+        const float in = ok && cn > 0 ? rcp((float)cn) : 0.f;
+        en[0][a] = ct == g0 ? in * i0n : 0.f;
+        en[1][a] = has1 && ct == g1 ? in * i1n : 0.f;
+        cq[0][a] = en[0][a] - (bt == g0 ? io * i0n : 0.f);
+        cq[1][a] = en[1][a] - (has1 && bt == g1 ? io * i1n : 0.f);
       }
       float cn_[2][3], cb_[2][3];
 #pragma unroll
@@ -1095,19 +1104,18 @@ __global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, Sc
           }
         }
       }
-      const int nb0 = (int)tab[L.nbg + g0] + d.dnb[0], nb1_ = (int)tab[L.nbg + g1] + d.dnb[1];
-      const float i0n = nb0 > 0 ? 1.f / (float)nb0 : 0.f, i1n = nb1_ > 0 ? 1.f / (float)nb1_ : 0.f;
-      const float du0 = d.u6[0] - tab[L.ub6 + g0], du1 = d.u6[1] - tab[L.ub6 + g1];
+      const float* rz0 = tab + L.rz + (3 * g0 + d.dnb[0] + 1) * kTabLd;
+      const float* rz1 = tab + L.rz + (3 * g1 + d.dnb[1] + 1) * kTabLd;
       const float f0 = (float)d.dnf[0], f1 = (float)d.dnf[1];
-      const float e0 = (float)d.dnb[0], e1 = (float)d.dnb[1];
+      const float u60 = d.u6[0], u61 = d.u6[1];
       float y00 = 0.f, y01 = 0.f, y10 = 0.f, y11 = 0.f;
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         // Bounds the loads in flight to one 4-column slice.
         __asm__ volatile("" ::: "memory");
         const int co = 16 * mt + 4 * q;
-        float4 s0 = *reinterpret_cast<const float4 *>(tab + L.r + g0 * kTabLd + co);
-        float4 s1 = *reinterpret_cast<const float4 *>(tab + L.r + g1 * kTabLd + co);
+        float4 s0 = *reinterpret_cast<const float4 *>(rz0 + co);
+        float4 s1 = *reinterpret_cast<const float4 *>(rz1 + co);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           const float4 t = *reinterpret_cast<const float4 *>(tab + L.q + qrow[a] * kTabLd + co);
@@ -1120,16 +1128,12 @@ __global__ __launch_bounds__(512, 1) void k_scr_fused(InstParams P, SurDev S, Sc
           s0 = fma4(cn_[0][k], pnk, fma4(-cb_[0][k], pb[k][mt], s0));
           s1 = fma4(cn_[1][k], pnk, fma4(-cb_[1][k], pb[k][mt], s1));
         }
-        const float4 u0 = *reinterpret_cast<const float4 *>(tab + L.u + g0 * kTabLd + co);
-        const float4 u1 = *reinterpret_cast<const float4 *>(tab + L.u + g1 * kTabLd + co);
         const float4 c4 = *reinterpret_cast<const float4 *>(tab + L.cst + co);
-        const float4 c5 = *reinterpret_cast<const float4 *>(tab + L.cst + kTabLd + co);
-        const float4 c6 = *reinterpret_cast<const float4 *>(tab + L.cst + 2 * kTabLd + co);
-        const float4 v0 = *reinterpret_cast<const float4 *>(tab + L.cst + 3 * kTabLd + co);
-        const float4 v1 = *reinterpret_cast<const float4 *>(tab + L.cst + 4 * kTabLd + co);
-        const float4 z0 = s0 * i0n + u0 + f0 * c4 + e0 * c5 + du0 * c6;
-        const float4 z1 = s1 * i1n + u1 + f1 * c4 + e1 * c5 + du1 * c6;
-        const float4 a0 = relu4(z0), a1 = relu4(z1);
+        const float4 c6 = *reinterpret_cast<const float4 *>(tab + L.cst + kTabLd + co);
+        const float4 v0 = *reinterpret_cast<const float4 *>(tab + L.cst + 2 * kTabLd + co);
+        const float4 v1 = *reinterpret_cast<const float4 *>(tab + L.cst + 3 * kTabLd + co);
+        const float4 a0 = relu4(fma4(u60, c6, fma4(f0, c4, s0)));
+        const float4 a1 = relu4(fma4(u61, c6, fma4(f1, c4, s1)));
         y00 += dot4(a0, v0);
         y01 += dot4(a0, v1);
         y10 += dot4(a1, v0);
@@ -1406,7 +1410,11 @@ __global__ void k_scr_check(InstParams P, ScreenDev T, const double *part, uint3
       const double mean = r1 / cnt, var = r2 / cnt - mean * mean;
       scatter = (float)(sqrt(var > 0.0 ? var : 0.0) / (ex / cnt));
     }
-    const bool lost = *T.ctrl_key < smin;
+    // The screen lost when the control sample improves on x* and beats the
+    // shortlist (late in a search neither improves, and the least bad move of
+    // an unscreened sample is no reason to evaluate the plain batch).
+    const uint64_t ck = *T.ctrl_key;
+    const bool lost = ck < smin && (ck >> 24) < P.st->cost_best;
     const uint32_t fb = (smin == kInfKey || lost || scatter > err_thr) ? 1u : 0u;
     *T.flag = fb;
     T.stats[0] = scatter;
@@ -1489,22 +1497,31 @@ int screen_waves(const InstParams &P) {
   return 0;
 }
 
-// Screen n_prop proposals against the base: base forward and tables, the
-// fused kernel's score keys, then the k best-predicted proposal indices into
-// T.short_idx.
-hipError_t launch_screen(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
-                         uint32_t inst_index, uint32_t n_prop, uint32_t k, float mk_margin,
-                         int n_cu, hipStream_t s) {
-  const int waves = screen_waves(P);
-  if (waves == 0) return hipErrorInvalidValue;
+// The screen of one iteration in three launches: the base's forward pass
+// and tables; the fused kernel's score keys of proposals 0 .. n_prop - 1;
+// the k best-predicted proposal indices into T.short_idx.
+hipError_t launch_screen_base(const InstParams &P, const SurDev &S, const ScreenDev &T, int n_cu,
+                              hipStream_t s) {
   hipError_t e = launch_sur_forward(P, S, nullptr, 1, 1, false, n_cu, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scr_tables, dim3(1), dim3(1024), 0, s, P, S, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_score(const InstParams &P, const SurDev &S, const ScreenDev &T, uint64_t seed,
+                               uint32_t inst_index, uint32_t n_prop, float mk_margin, int n_cu,
+                               hipStream_t s) {
+  const int waves = screen_waves(P);
+  if (waves == 0) return hipErrorInvalidValue;
   const uint32_t lds = fuse_layout(P.NB, P.NT, P.lay.total_words, waves).total;
   const uint32_t tasks = (n_prop + 63) / 64;
   const uint32_t grid = std::min<uint32_t>((tasks + waves - 1) / waves, (uint32_t)n_cu);
   hipLaunchKernelGGL(k_scr_fused, dim3(grid), dim3(64 * waves), lds, s, P, S, T, seed, inst_index, 0u,
                      n_prop, mk_margin);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_select(const ScreenDev &T, uint32_t n_prop, uint32_t k, hipStream_t s) {
   hipLaunchKernelGGL(k_sur_zero, dim3(8), dim3(256), 0, s, reinterpret_cast<float *>(T.hist), 2048u);
   hipLaunchKernelGGL(k_sur_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(T.sel), 8u);
   for (int pass = 0; pass < 3; ++pass) {

@@ -98,7 +98,8 @@ def test_screen_scores_match_full_forward(ctx, name, n, k):
 def _oracle_screened_step(inst, st, seed, n, eps, short, n_control):
     """The oracle's iteration over the shortlist and the control sample, or
     over every proposal when the exact results reject the screen (no gated
-    survivor in the shortlist, or the control sample beats it)."""
+    survivor in the shortlist, or the control sample beats it with a cost
+    below x*'s)."""
     seen = {}
 
     def key_of(job, i):
@@ -111,7 +112,7 @@ def _oracle_screened_step(inst, st, seed, n, eps, short, n_control):
     def keys(job, nn):
         smin = min(key_of(job, int(i)) for i in short)
         cmin = min((key_of(job, i) for i in range(n_control)), default=M.INF_KEY)
-        fallback = smin == M.INF_KEY or cmin < smin
+        fallback = smin == M.INF_KEY or (cmin < smin and (cmin >> 24) < st.cost_best)
         decision["fallback"] = fallback
         subset = range(nn) if fallback else set(int(i) for i in short) | set(range(n_control))
         out = [M.INF_KEY] * nn
@@ -151,6 +152,7 @@ def test_screened_iteration_matches_oracle_on_shortlist(ctx, name, n, k, n_contr
         fallbacks += fb
         _compare(ctx, iid, st, it)
     stats = ctx.sur_stats(sur)
+    _say("  fallbacks", fallbacks, "of", iters)
     assert stats["iterations"] == iters and stats["fallbacks"] == fallbacks
 
 
