@@ -158,7 +158,19 @@ struct SurDev {
   uint16_t *ex_btour;                 // [ex][NB] tour of each BP in the candidate
   float *ex_pred;                     // [ex][2] predicted (path, makespan), scaled
   float *loss;                        // [2] loss sum, examples counted
+  float *part_h;                      // [head waves][kHeadPart] per-wave sums of the head's gradients
+  float *part_b;                      // [backward workgroups][kBwdPart] per-workgroup sums
 };
+
+// Partial gradient sums of one training step.  Head, per wave: W3 rows of
+// the tour features (8 x 64), b3 (64), W4 (128), b4 (2), loss and count (2).
+// Backward, per workgroup: W1, W2, W3 rows 0..127, and b1, b2 in two halves.
+constexpr int kHeadPart = (kSurU + 3) * kSurA + 4;
+constexpr int kBwdW1 = 0, kBwdW2 = kBwdW1 + kSurIn * kSurH, kBwdW3 = kBwdW2 + kSurH * kSurH;
+constexpr int kBwdB1 = kBwdW3 + kSurH * kSurA, kBwdB2 = kBwdB1 + 2 * kSurH;
+constexpr int kBwdPart = kBwdB2 + 2 * kSurH;
+uint32_t sur_head_grid(uint32_t n, int n_cu);
+uint32_t sur_bwd_grid(uint32_t rows, int n_cu);
 
 // Screening of proposals through the learned screen.
 struct ScreenDesc {          // what one proposal changes relative to the base (64 bytes)

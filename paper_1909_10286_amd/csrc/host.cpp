@@ -1181,7 +1181,9 @@ bl_status bl_sur_create(bl_ctx *c, int32_t inst, const float *weights, const bl_
       (st = sur_alloc(c, R, D.ex_nb, (size_t)cfg->max_examples * NT)) ||
       (st = sur_alloc(c, R, D.ex_btour, (size_t)cfg->max_examples * NB)) ||
       (st = sur_alloc(c, R, D.ex_pred, (size_t)cfg->max_examples * 2)) ||
-      (st = sur_alloc(c, R, D.loss, 2))) {
+      (st = sur_alloc(c, R, D.loss, 2)) ||
+      (st = sur_alloc(c, R, D.part_h, (size_t)sur_head_grid(cfg->max_examples, c->n_cu) * 4 * kHeadPart)) ||
+      (st = sur_alloc(c, R, D.part_b, (size_t)sur_bwd_grid(rows, c->n_cu) * kBwdPart))) {
     for (void *p : R.allocs) (void)hipFree(p);
     return st;
   }

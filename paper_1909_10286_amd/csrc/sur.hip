@@ -337,15 +337,17 @@ __global__ __launch_bounds__(256) void k_sur_head(InstParams P, SurDev S, uint32
     for (int r = 0; r < P.NF; ++r) S.dP[(r0 + r) * kSurA + c] = Q[S.row_bp[r0 + r] * kSurA + c];
   }
   if (train) {
-    for (int j = 0; j < kSurU; ++j) atomicAdd(&S.G[kSurOffW3 + (kSurH + j) * kSurA + c], gw3u[j]);
-    atomicAdd(&S.G[kSurOffB3 + c], gb3);
-    atomicAdd(&S.G[kSurOffW4 + c * 2], gw40);
-    atomicAdd(&S.G[kSurOffW4 + c * 2 + 1], gw41);
+    // This wave's sums, added up in a fixed order by k_sur_gsum.
+    float *part = S.part_h + (size_t)(blockIdx.x * wpb + (threadIdx.x >> 6)) * kHeadPart;
+    for (int j = 0; j < kSurU; ++j) part[j * kSurA + c] = gw3u[j];
+    part[kSurU * kSurA + c] = gb3;
+    part[(kSurU + 1) * kSurA + 2 * c] = gw40;
+    part[(kSurU + 1) * kSurA + 2 * c + 1] = gw41;
     if (c == 0) {
-      atomicAdd(&S.G[kSurOffB4], gb40);
-      atomicAdd(&S.G[kSurOffB4 + 1], gb41);
-      atomicAdd(&S.loss[0], lsum);
-      atomicAdd(&S.loss[1], lcnt);
+      part[(kSurU + 3) * kSurA] = gb40;
+      part[(kSurU + 3) * kSurA + 1] = gb41;
+      part[(kSurU + 3) * kSurA + 2] = lsum;
+      part[(kSurU + 3) * kSurA + 3] = lcnt;
     }
   }
 }
@@ -453,37 +455,88 @@ __global__ __launch_bounds__(256) void k_sur_bwd(SurDev S, uint32_t n_rows) {
                      acc1[k]);
     }
   }
+  // This workgroup's sums (every entry written by exactly one lane), added
+  // up in a fixed order by k_sur_gsum.  The bias sums come in two halves,
+  // one per 16-row tile of the chunk.
+  float *part = S.part_b + (size_t)blockIdx.x * kBwdPart;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int tile = wave * 8 + k;
     for (int i = 0; i < 4; ++i)
-      atomicAdd(&S.G[kSurOffW3 + ((tile >> 2) * 16 + 4 * kb + i) * kSurA + (tile & 3) * 16 + r],
-                acc3[k][i]);
+      part[kBwdW3 + ((tile >> 2) * 16 + 4 * kb + i) * kSurA + (tile & 3) * 16 + r] = acc3[k][i];
   }
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int tile = wave * 16 + k;
     for (int i = 0; i < 4; ++i)
-      atomicAdd(&S.G[kSurOffW2 + ((tile >> 3) * 16 + 4 * kb + i) * kSurH + (tile & 7) * 16 + r],
-                acc2[k][i]);
+      part[kBwdW2 + ((tile >> 3) * 16 + 4 * kb + i) * kSurH + (tile & 7) * 16 + r] = acc2[k][i];
   }
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int tile = wave * 2 + k;
-    for (int i = 0; i < 4; ++i)
-      atomicAdd(&S.G[kSurOffW1 + (4 * kb + i) * kSurH + tile * 16 + r], acc1[k][i]);
+    for (int i = 0; i < 4; ++i) part[kBwdW1 + (4 * kb + i) * kSurH + tile * 16 + r] = acc1[k][i];
   }
   for (int k = 0; k < 4; ++k) {
-    const int nt = (wave * 4 + k) & 7;
+    const int tile = wave * 4 + k, rt = tile >> 3, nt = tile & 7;
     float v2 = gb2[k], v1 = gb1[k];
     v2 += __shfl_xor(v2, 16, 64);
     v2 += __shfl_xor(v2, 32, 64);
     v1 += __shfl_xor(v1, 16, 64);
     v1 += __shfl_xor(v1, 32, 64);
     if (kb == 0) {
-      atomicAdd(&S.G[kSurOffB2 + nt * 16 + r], v2);
-      atomicAdd(&S.G[kSurOffB1 + nt * 16 + r], v1);
+      part[kBwdB2 + rt * kSurH + nt * 16 + r] = v2;
+      part[kBwdB1 + rt * kSurH + nt * 16 + r] = v1;
     }
+  }
+}
+
+// Gradient (and loss) sums of one training step from the partial sums of
+// the head's waves and the backward pass's workgroups.  A workgroup of 16
+// waves takes 64 consecutive elements: wave w adds partials w, w + 16, ...
+// in order, then the 16 wave sums are added in order: the result does not
+// depend on scheduling.
+__device__ __forceinline__ int gsum_source(uint32_t i, uint32_t &o, uint32_t &o2) {
+  o2 = 0xFFFFFFFFu;
+  if (i >= (uint32_t)(kSurOffW3 + kSurH * kSurA)) {   // head: W3 rows of the tour features, b3, W4, b4
+    if (i < (uint32_t)kSurOffB3) o = i - (kSurOffW3 + kSurH * kSurA);
+    else if (i < (uint32_t)kSurOffW4) o = kSurU * kSurA + (i - kSurOffB3);
+    else if (i < (uint32_t)kSurOffB4) o = (kSurU + 1) * kSurA + (i - kSurOffW4);
+    else o = (kSurU + 3) * kSurA + (i - kSurOffB4);
+    return 0;
+  }
+  if (i < (uint32_t)kSurOffB1) o = kBwdW1 + (i - kSurOffW1);
+  else if (i < (uint32_t)kSurOffW2) o = kBwdB1 + (i - kSurOffB1), o2 = o + kSurH;
+  else if (i < (uint32_t)kSurOffB2) o = kBwdW2 + (i - kSurOffW2);
+  else if (i < (uint32_t)kSurOffW3) o = kBwdB2 + (i - kSurOffB2), o2 = o + kSurH;
+  else o = kBwdW3 + (i - kSurOffW3);
+  return 1;
+}
+
+__global__ __launch_bounds__(1024) void k_sur_gsum(SurDev S, uint32_t n_head, uint32_t n_bwd) {
+  __shared__ float red[16][65];
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // Elements kSurParams, kSurParams + 1 stand for the loss sum and count.
+  const uint32_t i = blockIdx.x * 64 + c;
+  float acc = 0.f;
+  if (i < (uint32_t)kSurParams + 2) {
+    uint32_t o, o2;
+    const int bwd = i < (uint32_t)kSurParams ? gsum_source(i, o, o2) : (o = (kSurU + 3) * kSurA + 2 + (i - kSurParams), o2 = 0xFFFFFFFFu, 0);
+    if (bwd) {
+      for (uint32_t b = w; b < n_bwd; b += 16) {
+        acc += S.part_b[(size_t)b * kBwdPart + o];
+        if (o2 != 0xFFFFFFFFu) acc += S.part_b[(size_t)b * kBwdPart + o2];
+      }
+    } else {
+      for (uint32_t h = w; h < n_head; h += 16) acc += S.part_h[(size_t)h * kHeadPart + o];
+    }
+  }
+  red[w][c] = acc;
+  __syncthreads();
+  if (w == 0 && i < (uint32_t)kSurParams + 2) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += red[k][c];
+    if (i < (uint32_t)kSurParams) S.G[i] = t;
+    else S.loss[i - kSurParams] = t;
   }
 }
 
@@ -1462,10 +1515,13 @@ hipError_t launch_sur_forward(const InstParams &P, const SurDev &S, const uint64
   return hipGetLastError();
 }
 
+uint32_t sur_head_grid(uint32_t n, int n_cu) { return std::min<uint32_t>((n + 3) / 4, (uint32_t)n_cu * 4); }
+uint32_t sur_bwd_grid(uint32_t rows, int n_cu) { return std::min<uint32_t>((rows + 31) / 32, (uint32_t)n_cu); }
+
 hipError_t launch_sur_head(const InstParams &P, const SurDev &S, uint32_t n, int train,
                            const float *cost_km, const int32_t *mk, int n_cu, hipStream_t s) {
   const size_t lds = (size_t)4 * P.NB * kSurA * 4;
-  const uint32_t gb = std::min<uint32_t>((n + 3) / 4, (uint32_t)n_cu * 4);
+  const uint32_t gb = sur_head_grid(n, n_cu);
   hipLaunchKernelGGL(k_sur_head, dim3(gb), dim3(256), lds, s, P, S, n, train, cost_km, mk);
   return hipGetLastError();
 }
@@ -1475,8 +1531,10 @@ hipError_t launch_sur_backward(const InstParams &P, const SurDev &S, uint32_t n,
   const uint32_t rows = n * (uint32_t)P.NF;
   const size_t lds = (size_t)(128 * kLd2 + 128 * kLd3 + 32 * kLd3 + 32 * kLd2 + 16 * kLd1 +
                               128 * kLd1 * 2 + 64 * kLd1 + 128 * kLd1 * 2) * 2;
-  const uint32_t gb = std::min<uint32_t>((rows + 31) / 32, (uint32_t)n_cu);
+  const uint32_t gb = sur_bwd_grid(rows, n_cu);
   hipLaunchKernelGGL(k_sur_bwd, dim3(gb), dim3(256), lds, s, S, rows);
+  hipLaunchKernelGGL(k_sur_gsum, dim3((kSurParams + 2 + 63) / 64), dim3(1024), 0, s, S,
+                     4 * sur_head_grid(n, n_cu), gb);
   return hipGetLastError();
 }
 

@@ -95,3 +95,25 @@ def test_adam_steps_reduce_loss(ctx):
         l = d_loss.cpu().numpy()
         losses.append(l[0] / max(l[1], 1))
     assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def test_training_is_deterministic(ctx):
+    """Gradient sums go through per-wave and per-workgroup partials added in
+    a fixed order, so two identical training runs give identical weights."""
+    _say("surrogate determinism")
+    inst, st, iid, sur, p, sc = setup(ctx, "mid100")
+    n = 512
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(iid, 9, 0, 0, 0, n, d_mv)
+    d_key = torch.empty(n, dtype=torch.int64, device="cuda")
+    d_c = torch.empty(n, dtype=torch.float32, device="cuda")
+    d_m = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.evaluate_batch(iid, d_mv, n, 1 << 40, d_key, d_c, d_m, None)
+    runs = []
+    for _ in range(2):
+        s = ctx.sur_create(iid, _flat(p), float(st.cost_best), float(st.t_best), max_examples=n)
+        for _ in range(5):
+            ctx.sur_train_step(s, d_mv, d_c, d_m, n)
+        runs.append(ctx.sur_get_weights(s))
+    assert not np.array_equal(runs[0], _flat(p).astype(np.float32))
+    assert np.array_equal(runs[0], runs[1])
