@@ -95,6 +95,48 @@ def test_screen_scores_match_full_forward(ctx, name, n, k):
     assert np.array_equal(short2, _expected_shortlist(score2, k))
 
 
+def test_screen_full_size_sampled(ctx):
+    """The screen at its full size (2^24 clust500 proposals, the bench's
+    launch): sampled scores, spread over the index range and including the
+    last proposal, equal the full forward pass of the same proposals; the
+    discards among them are exactly the eq. (2) breakers (gate off); and the
+    shortlist of 2^18 is the 2^18 smallest scores, lowest index first (its
+    boundary checked against the exported scores)."""
+    n, k = 1 << 24, 1 << 18
+    _say("screen full size", n, k)
+    inst, st, iid, sur, p, sc = setup(ctx, "clust500")
+    ctx.search_start(iid, 4)
+    seed, eps = 3, 1 << 32
+    short, score = _screen(ctx, sur, seed, eps, n, k, margin=1e9)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.choice(n, 1500, replace=False), [0, 63, 64, n - 64, n - 1]]))
+    d_all = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(iid, seed, 0, 0, 0, n, d_all)
+    d_mv = d_all[torch.from_numpy(idx).cuda()].contiguous()
+    del d_all
+    d_out = torch.empty(2 * len(idx), dtype=torch.float32, device="cuda")
+    ctx.sur_predict(sur, d_mv, len(idx), d_out)
+    torch.cuda.synchronize()
+    pred = d_out.cpu().numpy().reshape(-1, 2).astype(np.float64)
+    words = d_mv.cpu().numpy().view(np.uint64)
+    base = st.x_best
+    feas = np.array([M.is_feasible(inst, MV.apply_move(base, MV.decode(int(w)))) for w in words])
+    got = score[idx]
+    assert np.array_equal(np.isfinite(got), feas)
+    tol = 1e-4 * np.abs(pred[:, 0]).max() + 1e-6
+    assert np.abs(got[feas] - pred[feas, 0]).max() <= tol
+    # The shortlist: ascending, every member scores at most the k-th score, every
+    # non-member at least it, and among equal scores at the boundary the lowest indices.
+    assert len(short) == k and np.all(np.diff(short) > 0)
+    kth = np.partition(score, k - 1)[k - 1]
+    member = np.zeros(n, bool)
+    member[short] = True
+    assert (score[member] <= kth).all() and (score[~member] >= kth).all()
+    ties = np.nonzero(score == kth)[0]
+    n_below = int((score < kth).sum())
+    assert np.array_equal(np.nonzero(member & (score == kth))[0], ties[:k - n_below])
+
+
 def _oracle_screened_step(inst, st, seed, n, eps, short, n_control):
     """The oracle's iteration over the shortlist and the control sample, or
     over every proposal when the exact results reject the screen (no gated
