@@ -15,6 +15,7 @@
 
 #include "../../include/bl.h"
 #include "bl_internal.h"
+#include "sur_internal.h"
 
 namespace bl {
 int eval_occupancy(const InstParams &P, bool search);

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bl_internal.h"
+#include "sur_internal.h"
 #include "device.h"
 
 namespace bl {
