@@ -237,6 +237,31 @@ def test_screen_rejects_bad_sizes(ctx):
         ctx.sur_search_step(sur, 0, 0, 64, 8, 0, n_control=65)  # control beyond the proposals
 
 
+def test_screen_refuses_instance_beyond_lds(ctx):
+    """An instance whose image fits the evaluation kernel's LDS but not the
+    screen's (weights, tables and image in one workgroup) is evaluated, and
+    the screen calls refuse it with BL_EINVAL instead of launching."""
+    from oracle import init as OI
+    inst = inputs.make_custom_instance("big2000", 0, 200_000, 2000, 20, 10, 30, 120,
+                                       accept=OI.init_feasible)
+    iid = ctx.instance_upload(inst)
+    x0 = ctx.init_solution(iid)
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, 2)
+    ctx.search_step(iid, 0, 1 << 31, 4096)          # the evaluation runs
+    torch.cuda.synchronize()
+    st = ctx.search_state(iid)
+    w = bl.sur_glorot_weights(inputs.surrogate_init_words(1))
+    sur = ctx.sur_create(iid, w, float(st["cost_best_m"]), float(st["t_best_s"]), max_examples=8)
+    d = torch.empty(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(bl.BlError) as e:
+        ctx.sur_screen(sur, 0, 0, 4096, 64, d)
+    assert e.value.status == bl.EINVAL
+    with pytest.raises(bl.BlError) as e:
+        ctx.sur_search_step(sur, 0, 0, 4096, 64, 0)
+    assert e.value.status == bl.EINVAL
+
+
 def test_trained_screen_beats_random_shortlist(ctx):
     """What the trained network gains over the method without it: after a
     short training on exact labels along a plain trajectory, its shortlist of
