@@ -122,9 +122,24 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   const uint16_t *hu_rank = (const uint16_t *)(img + L.hu_rank);
   const uint16_t *su_rank = (const uint16_t *)(img + L.su_rank);
 
-  for (int i = tid; i <= P.NT; i += nt) tour_off[i] = x.tour_off[i];
-  for (int i = tid; i < P.NB; i += nt) tour_bp[i] = x.tour_bp[i];
-  for (int i = tid; i < P.NB; i += nt) bp_len[i] = (uint16_t)(x.bp_off[i + 1] - x.bp_off[i]);
+  // LDS copies of the tour lists and BP lengths for the serial prefix below
+  // (its reads then wait on LDS, not on global memory).
+  __shared__ uint16_t s_toff[kMaxTours + 1], s_tbp[kMaxBps], s_blen[kMaxBps];
+  for (int i = tid; i <= P.NT; i += nt) {
+    const uint16_t v = x.tour_off[i];
+    tour_off[i] = v;
+    s_toff[i] = v;
+  }
+  for (int i = tid; i < P.NB; i += nt) {
+    const uint16_t v = x.tour_bp[i];
+    tour_bp[i] = v;
+    s_tbp[i] = v;
+  }
+  for (int i = tid; i < P.NB; i += nt) {
+    const uint16_t v = (uint16_t)(x.bp_off[i + 1] - x.bp_off[i]);
+    bp_len[i] = v;
+    s_blen[i] = v;
+  }
   __syncthreads();
   uint16_t *t_start = (uint16_t *)(img + L.t_start), *t_end = (uint16_t *)(img + L.t_end);
   if (tid == 0) {
@@ -132,12 +147,12 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     uint32_t run = 0;
     for (int g = 0; g < P.NT; ++g) {
       t_start[g] = (uint16_t)run;
-      for (int j = x.tour_off[g]; j < x.tour_off[g + 1]; ++j) {
-        const int b = x.tour_bp[j];
+      for (int j = s_toff[g]; j < s_toff[g + 1]; ++j) {
+        const int b = s_tbp[j];
         bp_tour[b] = (uint16_t)g;
-        bp_idx[b] = (uint16_t)(j - x.tour_off[g]);
+        bp_idx[b] = (uint16_t)(j - s_toff[g]);
         bp_start[b] = (uint16_t)run;
-        run += bp_len[b];
+        run += s_blen[b];
       }
       t_end[g] = (uint16_t)run;
     }
@@ -180,6 +195,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   for (int b = tid; b < P.NB; b += nt) {
     uint32_t sd = 0, sup = 0, ar = 0, in = 0;
     uint64_t sh = 0;
+#pragma unroll 8
     for (int q = bp_start[b]; q < bp_start[b] + bp_len[b]; ++q) {
       const uint4 r = prec[q];
       sd += r.y;
@@ -230,6 +246,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     const int q0 = t_start[g], q1 = t_end[g];
     if (q1 > q0) {
       len = f_dhq[seq[q0]] + f_dhq[seq[q1 - 1]];
+#pragma unroll 8
       for (int q = q0 + 1; q < q1; ++q) len += prec[q].x;
     }
     t_len[g] = len;
@@ -243,18 +260,24 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     for (int b = 0; b < P.NB; ++b) v += b_sup[b] < demand[b] ? 1u : 0u;
     img[L.n_viol] = v;
   }
+  // Unit masks per tour: one thread per unit sets its rank bit (bitwise OR
+  // in LDS, so the order does not matter).
+  __shared__ unsigned long long s_hm[kMaxTours], s_sm[2 * kMaxTours];
   for (int g = tid; g < P.NT; g += nt) {
-    uint64_t hm = 0, lo = 0, hi = 0;
-    for (int h = 0; h < P.NHU; ++h)
-      if (x.hu_tour[h] == g) hm |= 1ull << hu_rank[h];
-    for (int s = 0; s < P.NSU; ++s)
-      if (x.su_tour[s] == g) {
-        const int r = su_rank[s];
-        if (r < 64) lo |= 1ull << r; else hi |= 1ull << (r - 64);
-      }
-    hu_mask[g] = hm;
-    su_mask[2 * g] = lo;
-    su_mask[2 * g + 1] = hi;
+    s_hm[g] = 0ull;
+    s_sm[2 * g] = s_sm[2 * g + 1] = 0ull;
+  }
+  __syncthreads();
+  for (int h = tid; h < P.NHU; h += nt) atomicOr(&s_hm[x.hu_tour[h]], 1ull << hu_rank[h]);
+  for (int u = tid; u < P.NSU; u += nt) {
+    const int r = su_rank[u];
+    atomicOr(&s_sm[2 * x.su_tour[u] + (r >> 6)], 1ull << (r & 63));
+  }
+  __syncthreads();
+  for (int g = tid; g < P.NT; g += nt) {
+    hu_mask[g] = s_hm[g];
+    su_mask[2 * g] = s_sm[2 * g];
+    su_mask[2 * g + 1] = s_sm[2 * g + 1];
   }
 }
 
