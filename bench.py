@@ -99,9 +99,15 @@ def cpu_baseline(inst, x0, n_sample):
     pool(job, n_sample)
     dt = time.perf_counter() - t0
     pool.close()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=n_sample / dt, unit="evals/s", cores=procs, kind="oracle",
                 sample="first %d candidates of iteration 0 (seed 0, eps 0.5), %d processes, %.1f s"
-                % (n_sample, procs, dt))
+                % (n_sample, procs, dt), cpu_model=model)
 
 
 def bench_batch(a):
@@ -490,6 +496,7 @@ def main():
         ctx.search_step(iid, seed, thr, n)
     eval_ms, launches = ctx.timing_read()
     ctx.timing_enable(False)
+    hbm_meas, lds_meas = ctx.measure_peaks()
     state = ctx.search_state(iid)
     secs = ms / 1e3
     value = n * a.steps / secs
@@ -519,10 +526,13 @@ def main():
                      "kernel": "k_eval (search mode)", "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
                      "kernel_ms_per_launch": per_launch_s * 1e3,
                      "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc},
+                             "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc,
+                             "peak_measured": lds_meas, "frac_measured": achieved / lds_meas},
                      "hbm": None if traffic is None else {
                          "achieved": traffic / per_launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": traffic / per_launch_s / 1e9 / HBM_PEAK_GBS}},
+                         "frac": traffic / per_launch_s / 1e9 / HBM_PEAK_GBS,
+                         "peak_measured": hbm_meas, "frac_measured": traffic / per_launch_s / 1e9 / hbm_meas}},
+        "measured_peaks": {"hbm_copy_gbs": hbm_meas, "lds_read_gbs": lds_meas},
         "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,
                    "iterations": state["it"], "wall_s": wall},
     }

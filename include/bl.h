@@ -375,6 +375,14 @@ bl_status bl_sur_stats_get(bl_ctx *ctx, int32_t sur, bl_sur_stats *out);
 bl_status bl_timing_enable(bl_ctx *ctx, int32_t what);
 bl_status bl_timing_read(bl_ctx *ctx, double *eval_ms, uint32_t *n_launches);
 
+/* Measured bandwidth peaks of the device, the denominators a roofline can
+ * use beside the published ones: *hbm_gbs from a streaming copy of 1 GiB
+ * (bytes read + written per second, best of 5 timed copies), *lds_gbs from
+ * conflict-free 16-byte LDS reads on every CU (bytes read per second, best
+ * of 5).  Either pointer may be null.  Allocates and frees 2 GiB of device
+ * memory; synchronises.  BL_ENOMEM if the buffers cannot be allocated. */
+bl_status bl_measure_peaks(bl_ctx *ctx, double *hbm_gbs, double *lds_gbs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -129,6 +129,7 @@ _SIGS = {
     "bl_sur_stats_get": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SurStats)]),
     "bl_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "bl_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint32)]),
+    "bl_measure_peaks": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -317,6 +318,12 @@ class Context:
         default) or of the screen's scoring kernel (TIMING_SCREEN)."""
         kind = TIMING_EVAL if kind is None else kind
         self._check(self._lib.bl_timing_enable(self._h, kind if on else 0))
+
+    def measure_peaks(self):
+        """(HBM GB/s from a streaming copy, LDS GB/s from ds_read_b128 streams)."""
+        h, l = C.c_double(), C.c_double()
+        self._check(self._lib.bl_measure_peaks(self._h, C.byref(h), C.byref(l)))
+        return h.value, l.value
 
     def timing_read(self):
         """(summed kernel ms, launches) of the timed kind since the last read."""

@@ -5,7 +5,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libbl.so")
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("eval.hip", "sur.hip", "host.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("eval.hip", "sur.hip", "peaks.hip", "host.cpp")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
          # Packed FP32 instructions stay off (see the build notes in the design doc).
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

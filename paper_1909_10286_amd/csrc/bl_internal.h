@@ -153,6 +153,13 @@ hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s);
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s);
 hipError_t launch_batch_commit(const BatchParams &B, size_t lds, hipStream_t s);
 
+// Bandwidth probes (peaks.hip): a streaming device copy of `bytes`; a
+// ds_read_b128 stream of `steps` reads per lane on peak_lds_blocks(n_cu)
+// workgroups of 256 lanes (out: one word per lane).
+hipError_t launch_peak_copy(const void *src, void *dst, size_t bytes, int n_cu, hipStream_t s);
+size_t peak_lds_blocks(int n_cu);
+hipError_t launch_peak_lds(uint32_t steps, uint32_t *out, int n_cu, hipStream_t s);
+
 enum { kPrepFromBase = 0, kPrepSearch = 1 };
 enum { kCommitStart = 0, kCommitStep = 1 };
 

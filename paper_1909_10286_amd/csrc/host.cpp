@@ -1427,6 +1427,56 @@ bl_status bl_timing_enable(bl_ctx *c, int32_t what) {
   return BL_OK;
 }
 
+bl_status bl_measure_peaks(bl_ctx *c, double *hbm_gbs, double *lds_gbs) {
+  if (!c) return BL_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  auto best_ms = [&](auto launch, float &out) -> hipError_t {
+    hipError_t e = launch();  // warm-up
+    if (e != hipSuccess) return e;
+    out = 1e30f;
+    for (int r = 0; r < 5; ++r) {
+      if ((e = hipEventRecord(e0, c->stream)) != hipSuccess || (e = launch()) != hipSuccess ||
+          (e = hipEventRecord(e1, c->stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+        return e;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+      out = std::min(out, ms);
+    }
+    return hipSuccess;
+  };
+  bl_status st = BL_OK;
+  if (hbm_gbs) {
+    const size_t bytes = (size_t)1 << 30;
+    void *a = nullptr, *b = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 1, bytes, c->stream);
+    float ms = 0.f;
+    if (e == hipSuccess) e = best_ms([&] { return launch_peak_copy(a, b, bytes, c->n_cu, c->stream); }, ms);
+    if (e == hipSuccess) *hbm_gbs = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
+    else st = hip_fail(c, e, "HBM copy probe");
+    (void)hipFree(a);
+    (void)hipFree(b);
+  }
+  if (lds_gbs && st == BL_OK) {
+    const uint32_t steps = 1u << 14;
+    const size_t lanes = peak_lds_blocks(c->n_cu) * 256;
+    uint32_t *out = nullptr;
+    hipError_t e = hipMalloc(&out, lanes * 4);
+    float ms = 0.f;
+    if (e == hipSuccess) e = best_ms([&] { return launch_peak_lds(steps, out, c->n_cu, c->stream); }, ms);
+    if (e == hipSuccess) *lds_gbs = (double)lanes * steps * 16.0 / (ms * 1e-3) / 1e9;
+    else st = hip_fail(c, e, "LDS read probe");
+    (void)hipFree(out);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 bl_status bl_timing_read(bl_ctx *c, double *eval_ms, uint32_t *n_launches) {
   if (!c || !eval_ms || !n_launches) return fail(c, BL_EINVAL, "null output");
   HIP_TRY(c, hipSetDevice(c->device));
