@@ -56,7 +56,11 @@ typedef int32_t bl_status;
                                  results; the walk is the plain reading of sec. 2.2) */
 #define BL_WIDE_KEYS 32u      /* 64-bit keys in the rebalancing rounds even where the
                                  instance's time bounds allow 32-bit ones (same
-                                 results) */
+                                 results; implies BL_SEGMENT_EVAL) */
+#define BL_SEGMENT_EVAL 64u   /* evaluate each candidate on a segment of lanes, one
+                                 tour per lane, also where the instance has at most
+                                 8 tours and one lane per candidate (all its tours in
+                                 registers) is the default (same results) */
 
 /* Per-candidate flags written by bl_evaluate_batch. */
 #define BL_CAND_INFEASIBLE 1u   /* eq. (2) violated; cost and makespan not evaluated */
@@ -104,7 +108,7 @@ typedef struct {
   const int32_t *xy_m;          /* [2 * V] or NULL: coordinates (learned screen features) */
   const uint16_t *init_hus_per_tour; /* [n_tours] or NULL: initial HU block sizes */
   const uint16_t *init_sus_per_tour; /* [n_tours] or NULL: initial SU block sizes */
-  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* | BL_FULL_WALK | BL_WIDE_KEYS */
+  uint32_t flags;               /* BL_FIXED_FIELD_BP | BL_NO_EMBEDDED_MIN | BL_GATE_* | BL_FULL_WALK | BL_WIDE_KEYS | BL_SEGMENT_EVAL */
   uint32_t cap_hu, cap_su;      /* rebalancing round caps; 0 = units + tours */
 } bl_instance;
 

@@ -17,7 +17,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbl.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EINFEASIBLE = 0, -1, -2, -3, -4, -5
-FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT, FULL_WALK, WIDE_KEYS = 1, 2, 4, 8, 16, 32
+FIXED_FIELD_BP, NO_EMBEDDED_MIN, GATE_OFF, GATE_STRICT, FULL_WALK, WIDE_KEYS, SEGMENT_EVAL = (
+    1, 2, 4, 8, 16, 32, 64)
 TIMING_EVAL = 1
 TIMING_SCREEN = 2
 CAND_INFEASIBLE, CAND_GATED, CAND_CAP_HU, CAND_CAP_SU, CAND_INVALID, CAND_INF_MAKESPAN = (

@@ -19,7 +19,7 @@ constexpr int64_t kNegInfT = INT64_MIN;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 enum : uint32_t { kFixedFieldBp = 1, kNoEmbeddedMin = 2, kGateOff = 4, kGateStrict = 8, kFullWalk = 16,
-                  kWideKeys = 32 };
+                  kWideKeys = 32, kSegmentEval = 64 };
 enum : uint32_t {
   kCandInfeasible = 1, kCandGated = 2, kCandCapHu = 4, kCandCapSu = 8, kCandInvalid = 16,
   kCandInfMakespan = 32
@@ -145,6 +145,9 @@ hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t 
                          hipStream_t s);
 hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStream_t s);
 size_t eval_lds_bytes(const InstParams &P);
+// Whether the evaluation launches take one candidate per lane (instances of
+// at most 8 tours, unless a flag asks for the segment version).
+bool lane_eval_on(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);
 int batch_occupancy(size_t lds, bool walk);

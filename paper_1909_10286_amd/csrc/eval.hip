@@ -22,6 +22,7 @@
 
 #include "bl_internal.h"
 #include "device.h"
+#include "lane_eval.h"
 
 namespace bl {
 
@@ -71,6 +72,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
     const CandResult r = eval_one<WALK>(V, P, w, ci, t, S, seg_base, seg_mask, t_star);
     if (MODE != kModeSearch && t == 0) {
+      if (out_key) out_key[c] = r.key;
+      if (out_cost) out_cost[c] = r.cost_km;
+      if (out_mk) out_mk[c] = r.mk;
+      if (out_flags) out_flags[c] = (uint8_t)r.flags;
+    }
+    best = r.key < best ? r.key : best;
+  }
+  if (MODE != kModeBatch) wave_min_to(best, P.best_key);
+}
+
+// The same launch with one candidate per lane (lane_eval.h): for instances of
+// at most kLaneMaxTours tours, unless a flag asks for the segment version.
+template <int N, bool DLDS, int MODE>
+__global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t *__restrict__ moves,
+                                                   uint32_t n, int64_t t_star_arg, uint64_t seed,
+                                                   uint32_t inst_index, uint64_t *__restrict__ out_key,
+                                                   float *__restrict__ out_cost,
+                                                   int32_t *__restrict__ out_mk,
+                                                   uint8_t *__restrict__ out_flags,
+                                                   const uint32_t *__restrict__ gather,
+                                                   const uint32_t *__restrict__ run_flag) {
+  if (run_flag && *run_flag == 0u) return;
+  __shared__ LaneBase s_base;
+  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
+  const uint32_t img_words = round4(P.lay.total_words);
+  stage(lds, P.image, P.lay.total_words);
+  if (DLDS) stage(lds + img_words, P.dist, (uint32_t)(P.V * P.V));
+  __syncthreads();
+  const View V = make_view(lds, P.lay, DLDS ? lds + img_words : P.dist);
+  if (threadIdx.x < N) {
+    const int t = threadIdx.x;
+    uint32_t R = 0, ld = 0;
+    for (uint64_t mm = V.hu_mask[t]; mm; mm &= mm - 1) R += V.hu_rate[__ffsll((unsigned long long)mm) - 1];
+    M128 sm{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
+    while (!m_empty(sm)) ld += V.su_fill[m_pop_low(sm)];
+    s_base.R[t] = R;
+    s_base.load[t] = ld;
+  }
+  __syncthreads();
+  uint32_t it = 0;
+  int64_t t_star = t_star_arg;
+  if (MODE != kModeBatch) {
+    it = P.st->it;
+    t_star = P.st->t_best;
+  }
+  uint64_t best = kInfKey;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+    const uint32_t ci = MODE == kModeGather ? gather[c] : c;
+    const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
+    const Move m = decode_move(w, V, P);
+    CandResult r{kInfKey, __builtin_inff(), 0x7FFFFFFF, 0u};
+    if (!m.valid) {
+      r.flags = kCandInvalid;
+    } else {
+      const LaneOut o = eval_lane<N>(V, P, s_base, m);
+      r.flags = o.flags;
+      if (o.feasible) {
+        r.cost_km = (float)((double)o.cost / 1000.0);
+        r.mk = o.makespan >= 0x7FFFFFFFll ? 0x7FFFFFFF : (int32_t)o.makespan;
+        if (is_gated(o.makespan, t_star, P.flags))
+          r.flags |= kCandGated;
+        else
+          r.key = (o.cost << 24) | (uint64_t)ci;
+      }
+    }
+    if (MODE != kModeSearch) {
       if (out_key) out_key[c] = r.key;
       if (out_cost) out_cost[c] = r.cost_km;
       if (out_mk) out_mk[c] = r.mk;
@@ -575,9 +643,24 @@ hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, ui
 
 // The instantiation for the instance: distance matrix in LDS or not, full
 // walk or delta evaluation.
+template <int MODE, bool DLDS, class... A>
+hipError_t launch_lane(const InstParams &P, int grid, size_t lds, hipStream_t s, A... a) {
+  switch (P.NT) {
+#define BL_LANE_CASE(N) \
+    case N: hipLaunchKernelGGL((k_eval_lane<N, DLDS, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
+    BL_LANE_CASE(1) BL_LANE_CASE(2) BL_LANE_CASE(3) BL_LANE_CASE(4)
+    BL_LANE_CASE(5) BL_LANE_CASE(6) BL_LANE_CASE(7) BL_LANE_CASE(8)
+#undef BL_LANE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int MODE, class... A>
 hipError_t launch_k_eval(const InstParams &P, int grid, hipStream_t s, A... a) {
   const size_t lds = eval_lds_bytes(P);
+  if (lane_eval_on(P))
+    return P.d_in_lds ? launch_lane<MODE, true>(P, grid, lds, s, a...) : launch_lane<MODE, false>(P, grid, lds, s, a...);
   const bool walk = (P.flags & kFullWalk) != 0;
   if (P.d_in_lds) {
     if (walk)
@@ -638,9 +721,32 @@ hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStr
   return hipGetLastError();
 }
 
+bool lane_eval_on(const InstParams &P) {
+  return P.NT >= 1 && P.NT <= kLaneMaxTours && !(P.flags & (kFullWalk | kWideKeys | kSegmentEval));
+}
+
+template <bool DLDS, int MODE>
+int lane_occupancy(const InstParams &P, size_t lds) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (P.NT) {
+#define BL_LANE_OCC(N) \
+    case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_lane<N, DLDS, MODE>, 256, lds); break;
+    BL_LANE_OCC(1) BL_LANE_OCC(2) BL_LANE_OCC(3) BL_LANE_OCC(4)
+    BL_LANE_OCC(5) BL_LANE_OCC(6) BL_LANE_OCC(7) BL_LANE_OCC(8)
+#undef BL_LANE_OCC
+    default: break;
+  }
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 int eval_occupancy(const InstParams &P, bool search) {
   int nb = 0;
   const size_t lds = eval_lds_bytes(P);
+  if (lane_eval_on(P)) {
+    if (P.d_in_lds) return search ? lane_occupancy<true, kModeSearch>(P, lds) : lane_occupancy<true, kModeBatch>(P, lds);
+    return search ? lane_occupancy<false, kModeSearch>(P, lds) : lane_occupancy<false, kModeBatch>(P, lds);
+  }
   hipError_t e;
   const bool walk = (P.flags & kFullWalk) != 0;
   if (P.d_in_lds)

@@ -228,7 +228,8 @@ bl_status alloc_trace(bl_ctx *c, Instance *I, uint32_t cap) {
 }
 
 int grid_for(const bl_ctx *c, const Instance &I, uint32_t n, bool search) {
-  const uint32_t per_block = 4u * (64u / (uint32_t)I.P.seg);
+  // Candidates one workgroup of 256 lanes takes at a time.
+  const uint32_t per_block = lane_eval_on(I.P) ? 256u : 4u * (64u / (uint32_t)I.P.seg);
   const uint32_t need = (n + per_block - 1) / per_block;
   const uint32_t cap = (uint32_t)c->n_cu * (uint32_t)(search ? I.occ_search : I.occ_batch);
   return (int)std::max<uint32_t>(1u, std::min(need, cap));
@@ -485,7 +486,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
       !in->su_cap_kg || !in->su_speed_mph || !in->su_fill_s)
     return fail(c, BL_EINVAL, "null instance array");
   if (in->hu_speed_mph == 0) return fail(c, BL_EINVAL, "hu_speed_mph must be > 0");
-  if (in->flags & ~63u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
+  if (in->flags & ~127u) return fail(c, BL_EINVAL, "unknown flags 0x%x", in->flags);
   auto I = std::make_unique<Instance>();
   I->NF = NF; I->NB = NB; I->NT = NT; I->NHU = NHU; I->NSU = NSU;
   const int V = 1 + NB + NF;

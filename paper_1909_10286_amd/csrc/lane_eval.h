@@ -1,0 +1,436 @@
+// One candidate per lane: the evaluation of device.h's segment version
+// (eval_candidate, delta mode) with every tour of the candidate in registers
+// of one lane instead of one tour per lane.  NTC is the instance's tour count
+// (compile time, at most kLaneMaxTours); per-tour values live in arrays that
+// the unrolled loops index with constants, and values of a tour picked at run
+// time (g_max, g_min) are read by select chains.  The rules, ties and integer
+// results are the segment version's, which the tests compare it with.
+#pragma once
+
+#include "device.h"
+
+namespace bl {
+
+namespace {
+
+constexpr int kLaneMaxTours = 8;
+
+// Base values per tour, the same for every candidate of a launch (one copy
+// per workgroup in LDS): rate sum of the tour's HUs and fill-time sum of its
+// SUs.
+struct LaneBase {
+  uint32_t R[kLaneMaxTours];
+  uint32_t load[kLaneMaxTours];
+};
+
+// The value in a VGPR as far as the optimiser knows, so that a select
+// chain over the tours stays a chain of selects instead of becoming an
+// indexed load from a stack copy of the array.
+template <class T>
+__device__ __forceinline__ T lopaque(T x) {
+  __asm__ volatile("" : "+v"(x));
+  return x;
+}
+
+template <int N, class T>
+__device__ __forceinline__ T lpick(const T (&a)[N], int i) {
+  T r = lopaque(a[0]);
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = i == k ? lopaque(a[k]) : r;
+  return r;
+}
+
+// What a move changes in the base's tour aggregates: the legs it cuts and
+// creates and the sums that travel with the moved field or BP (the segment
+// version's tour_delta, formed once for both tours).
+struct Change {
+  bool any;
+  int Ts, Td;
+  int64_t dLs, dLd;
+  uint32_t mv_area, mv_nf;
+  uint64_t sh_out, sh_in;
+  int32_t ms_s, ms_d, mc_s, mc_d;
+};
+
+__device__ __forceinline__ Change move_change(const View &V, const InstParams &P, const Move &m,
+                                              const Nbrs &nb) {
+  Change c;
+  c.any = nb.first >= 0;
+  const bool fm = m.kind == 0;
+  c.Ts = fm ? (int)V.bp_tour[m.src] : m.src;
+  c.Td = fm ? (int)V.bp_tour[m.dst] : m.dst;
+  c.dLs = c.dLd = 0;
+  c.mv_area = c.mv_nf = 0;
+  c.sh_out = c.sh_in = 0;
+  c.ms_s = c.ms_d = c.mc_s = c.mc_d = 0;
+  if (!c.any) return c;
+  const bool cross = fm && m.src != m.dst;
+  const size_t nb1 = 1 + (size_t)P.NB;
+  const uint32_t l_in = route_leg(V, P, nb.pnew, nb.first);
+  const uint32_t l_out = route_leg(V, P, nb.last, nb.nnew);
+  const uint32_t dfd = cross ? V.D[(nb1 + (size_t)m.v) * (size_t)P.V + 1 + (size_t)m.dst] : 0u;
+  const uint32_t bridge = fm ? V.skip[nb.q0] : V.b_skip[m.v];
+  const uint32_t lin = nb.pold < 0 ? V.dhq[nb.first] : V.prec[nb.q0].x;
+  const uint32_t lout = nb.nold < 0 ? V.dhq[nb.last] : V.prec[nb.q1].x;
+  const int64_t inner = fm ? 0 : (int64_t)V.b_int[m.v];
+  uint32_t gap;
+  if (nb.pnew == nb.pold && nb.nnew == nb.nold) {
+    gap = bridge;
+  } else if (nb.pnew < 0 || nb.nnew < 0) {
+    gap = nb.pnew < 0 ? (nb.nnew < 0 ? 0u : V.dhq[nb.nnew]) : V.dhq[nb.pnew];
+  } else {
+    const int qn = V.pos[nb.nnew];
+    gap = V.seq[qn - 1] == nb.pnew ? V.prec[qn].x : route_leg(V, P, nb.pnew, nb.nnew);
+  }
+  c.dLs = (int64_t)bridge - (int64_t)lin - (int64_t)lout - inner;
+  c.dLd = (int64_t)l_in + (int64_t)l_out - (int64_t)gap + inner;
+  if (fm) {
+    const int f = m.v;
+    c.mv_area = V.area[f];
+    c.mv_nf = 1;
+    c.sh_out = V.w_q[nb.q0];
+    c.sh_in = cross ? 2ull * (uint64_t)V.nsh[f] * (uint64_t)dfd : c.sh_out;
+    if (cross) {
+      const int bs = m.src, bd = m.dst;
+      const uint32_t cs = V.bp_len[bs], cd = V.bp_len[bd];
+      c.ms_s = (int32_t)bp_mean(V.b_sd[bs] - V.prec[nb.q0].y, cs - 1) - (int32_t)V.b_mean[bs];
+      c.mc_s = cs == 1 ? -1 : 0;
+      c.ms_d = (int32_t)bp_mean(V.b_sd[bd] + dfd, cd + 1) - (int32_t)V.b_mean[bd];
+      c.mc_d = cd == 0 ? 1 : 0;
+    }
+  } else {
+    const int b = m.v;
+    c.mv_area = V.b_area[b];
+    c.mv_nf = V.bp_len[b];
+    c.sh_out = c.sh_in = V.b_sh[b];
+    c.ms_s = -(int32_t)V.b_mean[b];
+    c.ms_d = (int32_t)V.b_mean[b];
+    c.mc_s = -1;
+    c.mc_d = 1;
+  }
+  return c;
+}
+
+__device__ __forceinline__ int64_t lane_tcompl(uint64_t lc, uint32_t A, uint32_t rate) {
+  return rate == 0 ? kInfT : (int64_t)(lc + udiv(3600ull * A, rate));
+}
+
+__device__ __forceinline__ int64_t lane_twait(const View &V, const M128 &msk, uint32_t ld, uint32_t nhu,
+                                              uint32_t dm) {
+  if (m_empty(msk) || nhu == 0) return kInfT;
+  const int s = m_top(msk);
+  const double r = 1.0 / (double)nhu;
+  return (int64_t)udiv(7200ull * dm, V.su_speed[s]) - (int64_t)udiv_small(ld - V.su_fill[s], nhu, r);
+}
+
+// Lowest-index arg-max over active tours (gmax, top) and over the others
+// (g2, second); -1 when there is none.
+template <int N>
+__device__ __forceinline__ void lane_top2(const int64_t (&v)[N], uint32_t actm, int &gmax, int64_t &top,
+                                          int &g2, int64_t &second) {
+  gmax = g2 = -1;
+  top = second = kNegInfT;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    if (!((actm >> t) & 1u)) continue;
+    if (gmax < 0 || v[t] > top) {
+      g2 = gmax;
+      second = top;
+      gmax = t;
+      top = v[t];
+    } else if (g2 < 0 || v[t] > second) {
+      g2 = t;
+      second = v[t];
+    }
+  }
+}
+
+template <int N>
+__device__ __forceinline__ int64_t lane_max(const int64_t (&v)[N], uint32_t actm) {
+  int64_t r = kNegInfT;
+#pragma unroll
+  for (int t = 0; t < N; ++t)
+    if ((actm >> t) & 1u) r = v[t] > r ? v[t] : r;
+  return r;
+}
+
+// Donors of a round: tours holding units outside {g_max, g2}, else outside
+// {g_max}; then the lowest-index arg-min of their key (the value of active
+// tours, -inf for inactive ones).  Returns -1 when there is no donor.
+template <int N>
+__device__ __forceinline__ int lane_gmin(const int64_t (&v)[N], uint32_t actm, uint32_t hasu, int gmax,
+                                         int g2) {
+  uint32_t dm = 0;
+#pragma unroll
+  for (int t = 0; t < N; ++t)
+    if (((hasu >> t) & 1u) && t != gmax && t != g2) dm |= 1u << t;
+  if (!dm) {
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      if (((hasu >> t) & 1u) && t != gmax) dm |= 1u << t;
+  }
+  if (!dm) return -1;
+  int g = -1;
+  int64_t best = 0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    if (!((dm >> t) & 1u)) continue;
+    const int64_t k = ((actm >> t) & 1u) ? v[t] : kNegInfT;
+    if (g < 0 || k < best) {
+      g = t;
+      best = k;
+    }
+  }
+  return g;
+}
+
+struct LaneOut {
+  uint64_t cost;
+  int64_t makespan;
+  uint32_t flags;
+  bool feasible;
+};
+
+template <int N>
+__device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
+                                             const Move &m) {
+  LaneOut o;
+  o.flags = 0;
+  const Nbrs nb = move_nbrs(V, m);
+  if (!delta_feasible(V, m)) {
+    o.feasible = false;
+    o.flags = kCandInfeasible;
+    o.cost = 0;
+    o.makespan = kInfT;
+    return o;
+  }
+  o.feasible = true;
+  const Change ch = move_change(V, P, m, nb);
+  // ---- tours of the candidate ----
+  uint32_t L[N], A[N], dm[N];
+  uint32_t actm = 0;
+  uint64_t shsum = 0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    int64_t Lx = V.t_len[t];
+    uint32_t a = V.t_area[t], ms = V.t_msum[t], mc = V.t_mcnt[t];
+    uint64_t sh = V.t_sh[t];
+    int nf = (int)V.t_end[t] - (int)V.t_start[t];
+    if (ch.any && t == ch.Ts) {
+      Lx += ch.dLs;
+      a -= ch.mv_area;
+      sh -= ch.sh_out;
+      ms = (uint32_t)((int32_t)ms + ch.ms_s);
+      mc = (uint32_t)((int32_t)mc + ch.mc_s);
+      nf -= (int)ch.mv_nf;
+    }
+    if (ch.any && t == ch.Td) {
+      Lx += ch.dLd;
+      a += ch.mv_area;
+      sh += ch.sh_in;
+      ms = (uint32_t)((int32_t)ms + ch.ms_d);
+      mc = (uint32_t)((int32_t)mc + ch.mc_d);
+      nf += (int)ch.mv_nf;
+    }
+    L[t] = (uint32_t)Lx;
+    A[t] = a;
+    dm[t] = mc ? ms / mc : 0u;
+    if (nf > 0) actm |= 1u << t;
+    shsum += sh;
+  }
+  uint64_t hm[N];
+  M128 sm[N];
+  uint32_t R[N], load[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    hm[t] = V.hu_mask[t];
+    sm[t] = M128{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
+    R[t] = B.R[t];
+    load[t] = B.load[t];
+  }
+  const bool embedded = !(P.flags & kNoEmbeddedMin);
+  // ---- HU min-max rebalancing: completion time ----
+  uint64_t lc[N];
+  int64_t T[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    lc[t] = udiv(3600ull * L[t], P.v_hu);
+    T[t] = ((actm >> t) & 1u) ? lane_tcompl(lc[t], A[t], R[t]) : 0;
+  }
+  if (embedded) {
+    int rounds = 0;
+    while (true) {
+      int gmax, g2;
+      int64_t top, t2;
+      lane_top2(T, actm, gmax, top, g2, t2);
+      if (gmax < 0) break;
+      const bool has2 = g2 >= 0;
+      uint32_t hasu = 0;
+#pragma unroll
+      for (int t = 0; t < N; ++t)
+        if (hm[t]) hasu |= 1u << t;
+      const int gmin = lane_gmin(T, actm, hasu, gmax, g2);
+      if (gmin < 0) break;
+      if (rounds == (int)P.cap_hu) {
+        o.flags |= kCandCapHu;
+        break;
+      }
+      uint64_t cands = lpick(hm, gmin);
+      const uint64_t lcx = lpick(lc, gmax);
+      const uint32_t ax = lpick(A, gmax), rx = lpick(R, gmax);
+      int u = 0;
+      while (cands) {
+        u = __ffsll((unsigned long long)cands) - 1;
+        cands &= cands - 1;
+        const int64_t trial = (int64_t)(lcx + udiv(3600ull * ax, rx + V.hu_rate[u]));
+        if (!has2 || trial < t2 || cands == 0) break;
+      }
+      const uint32_t ru = V.hu_rate[u];
+      const uint64_t bit = 1ull << u;
+      const int64_t Tmin0 = lpick(T, gmin), Tmax0 = lpick(T, gmax);
+      // The two tours that change, recomputed (inactive tours keep their value).
+      const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
+      const int64_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
+      const int64_t Tmax1 = ((actm >> gmax) & 1u) ? lane_tcompl(lcx, ax, Rmax) : Tmax0;
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        if (t == gmin) {
+          hm[t] &= ~bit;
+          R[t] = Rmin;
+          T[t] = Tmin1;
+        }
+        if (t == gmax) {
+          hm[t] |= bit;
+          R[t] = Rmax;
+          T[t] = Tmax1;
+        }
+      }
+      ++rounds;
+      if (lane_max(T, actm) < top) continue;
+      // Not kept: undo.
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        if (t == gmin) {
+          hm[t] |= bit;
+          R[t] += ru;
+          T[t] = Tmin0;
+        }
+        if (t == gmax) {
+          hm[t] &= ~bit;
+          R[t] -= ru;
+          T[t] = Tmax0;
+        }
+      }
+      break;
+    }
+  }
+  const int64_t tmax = lane_max(T, actm);
+  // ---- SU min-max rebalancing, Alg. 2: waiting time ----
+  uint32_t nhu[N];
+  int64_t W[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    nhu[t] = (uint32_t)__popcll(hm[t]);
+    W[t] = ((actm >> t) & 1u) ? lane_twait(V, sm[t], load[t], nhu[t], dm[t]) : 0;
+  }
+  if (embedded) {
+    int rounds = 0;
+    while (true) {
+      int gmax, g2;
+      int64_t top, w2;
+      lane_top2(W, actm, gmax, top, g2, w2);
+      if (gmax < 0) break;
+      const bool has2 = g2 >= 0;
+      uint32_t hasu = 0;
+#pragma unroll
+      for (int t = 0; t < N; ++t)
+        if (!m_empty(sm[t])) hasu |= 1u << t;
+      const int gmin = lane_gmin(W, actm, hasu, gmax, g2);
+      if (gmin < 0) break;
+      if (rounds == (int)P.cap_su) {
+        o.flags |= kCandCapSu;
+        break;
+      }
+      uint64_t slo[N], shi[N];
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        slo[t] = sm[t].lo;
+        shi[t] = sm[t].hi;
+      }
+      M128 cands{lpick(slo, gmin), lpick(shi, gmin)}, smx{lpick(slo, gmax), lpick(shi, gmax)};
+      const int topx = m_empty(smx) ? -1 : m_top(smx);
+      const uint32_t ldx = lpick(load, gmax), nhx = lpick(nhu, gmax), dmx = lpick(dm, gmax);
+      const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
+      const double r_nhx = nhx ? 1.0 / (double)nhx : 0.0;
+      int u = 0;
+      while (!m_empty(cands)) {
+        u = m_pop_low(cands);
+        int64_t trial;
+        if (nhx == 0) {
+          trial = kInfT;
+        } else {
+          const int s = u > topx ? u : topx;
+          const uint32_t ld = ldx + V.su_fill[u];
+          const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
+          trial = (int64_t)rt - (int64_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
+        }
+        if (!has2 || trial < w2 || m_empty(cands)) break;
+      }
+      const uint32_t fu = V.su_fill[u];
+      const int64_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        if (t == gmin) {
+          m_clear(sm[t], u);
+          load[t] -= fu;
+        }
+        if (t == gmax) {
+          m_set(sm[t], u);
+          load[t] += fu;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        slo[t] = sm[t].lo;
+        shi[t] = sm[t].hi;
+      }
+      const M128 smin_new{lpick(slo, gmin), lpick(shi, gmin)}, smax_new{lpick(slo, gmax), lpick(shi, gmax)};
+      const int64_t Wmin1 = ((actm >> gmin) & 1u)
+                                ? lane_twait(V, smin_new, lpick(load, gmin), lpick(nhu, gmin), lpick(dm, gmin))
+                                : Wmin0;
+      const int64_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, smax_new, ldx + fu, nhx, dmx) : Wmax0;
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        if (t == gmin) W[t] = Wmin1;
+        if (t == gmax) W[t] = Wmax1;
+      }
+      ++rounds;
+      if (lane_max(W, actm) < top) continue;
+      // Not kept: undo (W is not used after the loop).
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        if (t == gmin) {
+          m_set(sm[t], u);
+          load[t] += fu;
+        }
+        if (t == gmax) {
+          m_clear(sm[t], u);
+          load[t] -= fu;
+        }
+      }
+      break;
+    }
+  }
+  // ---- path length (sec. 2.2) ----
+  uint64_t cost = shsum;
+#pragma unroll
+  for (int t = 0; t < N; ++t) cost += (uint64_t)(__popcll(hm[t]) + m_pop(sm[t])) * (uint64_t)L[t];
+  o.cost = cost;
+  o.makespan = tmax;
+  if (tmax == kInfT) o.flags |= kCandInfMakespan;
+  return o;
+}
+
+}  // namespace
+
+}  // namespace bl
