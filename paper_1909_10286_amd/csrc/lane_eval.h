@@ -125,6 +125,7 @@ __device__ __forceinline__ int64_t lane_twait(const View &V, const M128 &msk, ui
 
 // Lowest-index arg-max over active tours (gmax, top) and over the others
 // (g2, second); -1 when there is none.
+// (Branch-free: every step is a select, so the lanes of a wave never split.)
 template <int N>
 __device__ __forceinline__ void lane_top2(const int64_t (&v)[N], uint32_t actm, int &gmax, int64_t &top,
                                           int &g2, int64_t &second) {
@@ -132,16 +133,13 @@ __device__ __forceinline__ void lane_top2(const int64_t (&v)[N], uint32_t actm, 
   top = second = kNegInfT;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    if (!((actm >> t) & 1u)) continue;
-    if (gmax < 0 || v[t] > top) {
-      g2 = gmax;
-      second = top;
-      gmax = t;
-      top = v[t];
-    } else if (g2 < 0 || v[t] > second) {
-      g2 = t;
-      second = v[t];
-    }
+    const bool a = (actm >> t) & 1u;
+    const bool up1 = a && (gmax < 0 || v[t] > top);
+    const bool up2 = a && !up1 && (g2 < 0 || v[t] > second);
+    g2 = up1 ? gmax : (up2 ? t : g2);
+    second = up1 ? top : (up2 ? v[t] : second);
+    gmax = up1 ? t : gmax;
+    top = up1 ? v[t] : top;
   }
 }
 
@@ -149,8 +147,7 @@ template <int N>
 __device__ __forceinline__ int64_t lane_max(const int64_t (&v)[N], uint32_t actm) {
   int64_t r = kNegInfT;
 #pragma unroll
-  for (int t = 0; t < N; ++t)
-    if ((actm >> t) & 1u) r = v[t] > r ? v[t] : r;
+  for (int t = 0; t < N; ++t) r = (((actm >> t) & 1u) && v[t] > r) ? v[t] : r;
   return r;
 }
 
@@ -160,26 +157,17 @@ __device__ __forceinline__ int64_t lane_max(const int64_t (&v)[N], uint32_t actm
 template <int N>
 __device__ __forceinline__ int lane_gmin(const int64_t (&v)[N], uint32_t actm, uint32_t hasu, int gmax,
                                          int g2) {
-  uint32_t dm = 0;
-#pragma unroll
-  for (int t = 0; t < N; ++t)
-    if (((hasu >> t) & 1u) && t != gmax && t != g2) dm |= 1u << t;
-  if (!dm) {
-#pragma unroll
-    for (int t = 0; t < N; ++t)
-      if (((hasu >> t) & 1u) && t != gmax) dm |= 1u << t;
-  }
-  if (!dm) return -1;
+  const uint32_t not_max = gmax >= 0 ? ~(1u << gmax) : ~0u, not_2 = g2 >= 0 ? ~(1u << g2) : ~0u;
+  const uint32_t d1 = hasu & not_max & not_2, d2 = hasu & not_max;
+  const uint32_t dm = d1 ? d1 : d2;
   int g = -1;
   int64_t best = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    if (!((dm >> t) & 1u)) continue;
     const int64_t k = ((actm >> t) & 1u) ? v[t] : kNegInfT;
-    if (g < 0 || k < best) {
-      g = t;
-      best = k;
-    }
+    const bool take = ((dm >> t) & 1u) && (g < 0 || k < best);
+    g = take ? t : g;
+    best = take ? k : best;
   }
   return g;
 }
@@ -292,36 +280,20 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
       const int64_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
       const int64_t Tmax1 = ((actm >> gmax) & 1u) ? lane_tcompl(lcx, ax, Rmax) : Tmax0;
+      // The new times of every tour, kept only if the maximum falls.
+      int64_t Tn[N];
 #pragma unroll
-      for (int t = 0; t < N; ++t) {
-        if (t == gmin) {
-          hm[t] &= ~bit;
-          R[t] = Rmin;
-          T[t] = Tmin1;
-        }
-        if (t == gmax) {
-          hm[t] |= bit;
-          R[t] = Rmax;
-          T[t] = Tmax1;
-        }
-      }
+      for (int t = 0; t < N; ++t) Tn[t] = t == gmin ? Tmin1 : (t == gmax ? Tmax1 : T[t]);
       ++rounds;
-      if (lane_max(T, actm) < top) continue;
-      // Not kept: undo.
+      const bool keep = lane_max(Tn, actm) < top;
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        if (t == gmin) {
-          hm[t] |= bit;
-          R[t] += ru;
-          T[t] = Tmin0;
-        }
-        if (t == gmax) {
-          hm[t] &= ~bit;
-          R[t] -= ru;
-          T[t] = Tmax0;
-        }
+        const bool mn = keep && t == gmin, mx = keep && t == gmax;
+        hm[t] = mn ? (hm[t] & ~bit) : (mx ? (hm[t] | bit) : hm[t]);
+        R[t] = mn ? Rmin : (mx ? Rmax : R[t]);
+        T[t] = keep ? Tn[t] : T[t];
       }
-      break;
+      if (!keep) break;
     }
   }
   const int64_t tmax = lane_max(T, actm);
@@ -357,7 +329,8 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         slo[t] = sm[t].lo;
         shi[t] = sm[t].hi;
       }
-      M128 cands{lpick(slo, gmin), lpick(shi, gmin)}, smx{lpick(slo, gmax), lpick(shi, gmax)};
+      const M128 cands_all{lpick(slo, gmin), lpick(shi, gmin)}, smx{lpick(slo, gmax), lpick(shi, gmax)};
+      M128 cands = cands_all;
       const int topx = m_empty(smx) ? -1 : m_top(smx);
       const uint32_t ldx = lpick(load, gmax), nhx = lpick(nhu, gmax), dmx = lpick(dm, gmax);
       const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
@@ -378,47 +351,29 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       }
       const uint32_t fu = V.su_fill[u];
       const int64_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
-#pragma unroll
-      for (int t = 0; t < N; ++t) {
-        if (t == gmin) {
-          m_clear(sm[t], u);
-          load[t] -= fu;
-        }
-        if (t == gmax) {
-          m_set(sm[t], u);
-          load[t] += fu;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < N; ++t) {
-        slo[t] = sm[t].lo;
-        shi[t] = sm[t].hi;
-      }
-      const M128 smin_new{lpick(slo, gmin), lpick(shi, gmin)}, smax_new{lpick(slo, gmax), lpick(shi, gmax)};
+      // The two tours after the move, then the new times of every tour, kept
+      // only if the maximum falls.
+      const uint64_t ulo = u < 64 ? 1ull << u : 0ull, uhi = u < 64 ? 0ull : 1ull << (u - 64);
+      const M128 smin_new{cands_all.lo & ~ulo, cands_all.hi & ~uhi}, smax_new{smx.lo | ulo, smx.hi | uhi};
+      const uint32_t ldmin = lpick(load, gmin) - fu;
       const int64_t Wmin1 = ((actm >> gmin) & 1u)
-                                ? lane_twait(V, smin_new, lpick(load, gmin), lpick(nhu, gmin), lpick(dm, gmin))
+                                ? lane_twait(V, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
                                 : Wmin0;
       const int64_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, smax_new, ldx + fu, nhx, dmx) : Wmax0;
+      int64_t Wn[N];
 #pragma unroll
-      for (int t = 0; t < N; ++t) {
-        if (t == gmin) W[t] = Wmin1;
-        if (t == gmax) W[t] = Wmax1;
-      }
+      for (int t = 0; t < N; ++t) Wn[t] = t == gmin ? Wmin1 : (t == gmax ? Wmax1 : W[t]);
       ++rounds;
-      if (lane_max(W, actm) < top) continue;
-      // Not kept: undo (W is not used after the loop).
+      const bool keep = lane_max(Wn, actm) < top;
 #pragma unroll
       for (int t = 0; t < N; ++t) {
-        if (t == gmin) {
-          m_set(sm[t], u);
-          load[t] += fu;
-        }
-        if (t == gmax) {
-          m_clear(sm[t], u);
-          load[t] -= fu;
-        }
+        const bool mn = keep && t == gmin, mx = keep && t == gmax;
+        sm[t].lo = mn ? smin_new.lo : (mx ? smax_new.lo : sm[t].lo);
+        sm[t].hi = mn ? smin_new.hi : (mx ? smax_new.hi : sm[t].hi);
+        load[t] = mn ? ldmin : (mx ? ldx + fu : load[t]);
+        W[t] = keep ? Wn[t] : W[t];
       }
-      break;
+      if (!keep) break;
     }
   }
   // ---- path length (sec. 2.2) ----

@@ -159,6 +159,9 @@ CASES = [
     ("mid100", 2085, "walk", bl.WIDE_KEYS, (0, 0), "big"),
     ("clust500", 129, "init", bl.WIDE_KEYS | bl.FULL_WALK, (2, 3), "base"),
     ("batch31", 500, "init", bl.WIDE_KEYS, (1, 1), "big"),
+    # The segment version (one tour per lane) where one lane per candidate is the default.
+    ("mid100", 2085, "walk", bl.SEGMENT_EVAL, (0, 0), "big"),
+    ("tiny12", 1000, "inactive", bl.SEGMENT_EVAL, (0, 0), "base"),
 ]
 
 
@@ -185,9 +188,10 @@ def test_evaluate_batch_parity(ctx, name, n, kind, flags, caps, tk):
 @pytest.mark.parametrize("name,kind", [("mid100", "walk"), ("clust500", "walk"), ("batch77", "init"),
                                        ("mid100", "emptybp"), ("tiny12", "inactive")])
 def test_delta_equals_full_walk(ctx, name, kind):
-    """The default evaluation (base aggregates plus the legs a move changes,
-    32-bit rebalancing keys), the full walk and the 64-bit keys agree bit for
-    bit on 2^16 generated moves."""
+    """The default evaluation (base aggregates plus the legs a move changes;
+    one candidate per lane up to 8 tours, else 32-bit rebalancing keys on a
+    segment of lanes), the segment version, the full walk and the 64-bit keys
+    agree bit for bit on 2^16 generated moves."""
     _say("delta vs walk", name, kind)
     inst = _instance(name)
     base = {"init": lambda: OI.init_solution(inst), "walk": lambda: _walk_base(inst, OI.init_solution(inst), 5, 40),
@@ -195,13 +199,14 @@ def test_delta_equals_full_walk(ctx, name, kind):
     a = _setup(ctx, inst, base)
     b = _setup(ctx, inst, base, bl.FULL_WALK)
     w = _setup(ctx, inst, base, bl.WIDE_KEYS)
+    g = _setup(ctx, inst, base, bl.SEGMENT_EVAL)
     n = 1 << 16
     d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
     ctx.generate(a, 77, 5, 0, 0, n, d_mv)
     words = d_mv.cpu().numpy().view(np.uint64)
     for t_star in (1 << 40, int(M.evaluate_solution(inst, base).makespan_s) if kind != "emptybp" else 0):
         ga = _gpu_eval(ctx, a, words, t_star)
-        for other in (b, w):
+        for other in (b, w, g):
             go = _gpu_eval(ctx, other, words, t_star)
             for x, y in zip(ga, go):
                 assert np.array_equal(x, y)
