@@ -722,7 +722,7 @@ hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStr
 }
 
 bool lane_eval_on(const InstParams &P) {
-  return P.NT >= 1 && P.NT <= kLaneMaxTours && !(P.flags & (kFullWalk | kWideKeys | kSegmentEval));
+  return P.narrow && P.NT >= 1 && P.NT <= kLaneMaxTours && !(P.flags & (kFullWalk | kWideKeys | kSegmentEval));
 }
 
 template <bool DLDS, int MODE>

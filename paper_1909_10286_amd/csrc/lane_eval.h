@@ -15,6 +15,13 @@ namespace {
 
 constexpr int kLaneMaxTours = 8;
 
+// Times in the rounds: 32-bit, which the instance's time bounds allow (the
+// lane version runs only on instances whose completion and waiting times
+// stay within (-2^26, 2^26), checked at upload); +inf and -inf are the
+// extremes of the type.
+using tm_t = int32_t;
+constexpr tm_t kTInf = INT32_MAX, kTNegInf = INT32_MIN;
+
 // Base values per tour, the same for every candidate of a launch (one copy
 // per workgroup in LDS): rate sum of the tour's HUs and fill-time sum of its
 // SUs.
@@ -111,26 +118,26 @@ __device__ __forceinline__ Change move_change(const View &V, const InstParams &P
   return c;
 }
 
-__device__ __forceinline__ int64_t lane_tcompl(uint64_t lc, uint32_t A, uint32_t rate) {
-  return rate == 0 ? kInfT : (int64_t)(lc + udiv(3600ull * A, rate));
+__device__ __forceinline__ tm_t lane_tcompl(uint32_t lc, uint32_t A, uint32_t rate) {
+  return rate == 0 ? kTInf : (tm_t)(lc + (uint32_t)udiv(3600ull * A, rate));
 }
 
-__device__ __forceinline__ int64_t lane_twait(const View &V, const M128 &msk, uint32_t ld, uint32_t nhu,
-                                              uint32_t dm) {
-  if (m_empty(msk) || nhu == 0) return kInfT;
+__device__ __forceinline__ tm_t lane_twait(const View &V, const M128 &msk, uint32_t ld, uint32_t nhu,
+                                           uint32_t dm) {
+  if (m_empty(msk) || nhu == 0) return kTInf;
   const int s = m_top(msk);
   const double r = 1.0 / (double)nhu;
-  return (int64_t)udiv(7200ull * dm, V.su_speed[s]) - (int64_t)udiv_small(ld - V.su_fill[s], nhu, r);
+  return (tm_t)udiv(7200ull * dm, V.su_speed[s]) - (tm_t)udiv_small(ld - V.su_fill[s], nhu, r);
 }
 
 // Lowest-index arg-max over active tours (gmax, top) and over the others
 // (g2, second); -1 when there is none.
 // (Branch-free: every step is a select, so the lanes of a wave never split.)
 template <int N>
-__device__ __forceinline__ void lane_top2(const int64_t (&v)[N], uint32_t actm, int &gmax, int64_t &top,
-                                          int &g2, int64_t &second) {
+__device__ __forceinline__ void lane_top2(const tm_t (&v)[N], uint32_t actm, int &gmax, tm_t &top,
+                                          int &g2, tm_t &second) {
   gmax = g2 = -1;
-  top = second = kNegInfT;
+  top = second = kTNegInf;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     const bool a = (actm >> t) & 1u;
@@ -144,8 +151,8 @@ __device__ __forceinline__ void lane_top2(const int64_t (&v)[N], uint32_t actm, 
 }
 
 template <int N>
-__device__ __forceinline__ int64_t lane_max(const int64_t (&v)[N], uint32_t actm) {
-  int64_t r = kNegInfT;
+__device__ __forceinline__ tm_t lane_max(const tm_t (&v)[N], uint32_t actm) {
+  tm_t r = kTNegInf;
 #pragma unroll
   for (int t = 0; t < N; ++t) r = (((actm >> t) & 1u) && v[t] > r) ? v[t] : r;
   return r;
@@ -155,16 +162,16 @@ __device__ __forceinline__ int64_t lane_max(const int64_t (&v)[N], uint32_t actm
 // {g_max}; then the lowest-index arg-min of their key (the value of active
 // tours, -inf for inactive ones).  Returns -1 when there is no donor.
 template <int N>
-__device__ __forceinline__ int lane_gmin(const int64_t (&v)[N], uint32_t actm, uint32_t hasu, int gmax,
+__device__ __forceinline__ int lane_gmin(const tm_t (&v)[N], uint32_t actm, uint32_t hasu, int gmax,
                                          int g2) {
   const uint32_t not_max = gmax >= 0 ? ~(1u << gmax) : ~0u, not_2 = g2 >= 0 ? ~(1u << g2) : ~0u;
   const uint32_t d1 = hasu & not_max & not_2, d2 = hasu & not_max;
   const uint32_t dm = d1 ? d1 : d2;
   int g = -1;
-  int64_t best = 0;
+  tm_t best = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    const int64_t k = ((actm >> t) & 1u) ? v[t] : kNegInfT;
+    const tm_t k = ((actm >> t) & 1u) ? v[t] : kTNegInf;
     const bool take = ((dm >> t) & 1u) && (g < 0 || k < best);
     g = take ? t : g;
     best = take ? k : best;
@@ -238,18 +245,18 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   }
   const bool embedded = !(P.flags & kNoEmbeddedMin);
   // ---- HU min-max rebalancing: completion time ----
-  uint64_t lc[N];
-  int64_t T[N];
+  uint32_t lc[N];
+  tm_t T[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    lc[t] = udiv(3600ull * L[t], P.v_hu);
+    lc[t] = (uint32_t)udiv(3600ull * L[t], P.v_hu);
     T[t] = ((actm >> t) & 1u) ? lane_tcompl(lc[t], A[t], R[t]) : 0;
   }
   if (embedded) {
     int rounds = 0;
     while (true) {
       int gmax, g2;
-      int64_t top, t2;
+      tm_t top, t2;
       lane_top2(T, actm, gmax, top, g2, t2);
       if (gmax < 0) break;
       const bool has2 = g2 >= 0;
@@ -264,24 +271,24 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         break;
       }
       uint64_t cands = lpick(hm, gmin);
-      const uint64_t lcx = lpick(lc, gmax);
+      const uint32_t lcx = lpick(lc, gmax);
       const uint32_t ax = lpick(A, gmax), rx = lpick(R, gmax);
       int u = 0;
       while (cands) {
         u = __ffsll((unsigned long long)cands) - 1;
         cands &= cands - 1;
-        const int64_t trial = (int64_t)(lcx + udiv(3600ull * ax, rx + V.hu_rate[u]));
+        const tm_t trial = (tm_t)(lcx + (uint32_t)udiv(3600ull * ax, rx + V.hu_rate[u]));
         if (!has2 || trial < t2 || cands == 0) break;
       }
       const uint32_t ru = V.hu_rate[u];
       const uint64_t bit = 1ull << u;
-      const int64_t Tmin0 = lpick(T, gmin), Tmax0 = lpick(T, gmax);
+      const tm_t Tmin0 = lpick(T, gmin), Tmax0 = lpick(T, gmax);
       // The two tours that change, recomputed (inactive tours keep their value).
       const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
-      const int64_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
-      const int64_t Tmax1 = ((actm >> gmax) & 1u) ? lane_tcompl(lcx, ax, Rmax) : Tmax0;
+      const tm_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
+      const tm_t Tmax1 = ((actm >> gmax) & 1u) ? lane_tcompl(lcx, ax, Rmax) : Tmax0;
       // The new times of every tour, kept only if the maximum falls.
-      int64_t Tn[N];
+      tm_t Tn[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) Tn[t] = t == gmin ? Tmin1 : (t == gmax ? Tmax1 : T[t]);
       ++rounds;
@@ -296,10 +303,10 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       if (!keep) break;
     }
   }
-  const int64_t tmax = lane_max(T, actm);
+  const tm_t tmax = lane_max(T, actm);
   // ---- SU min-max rebalancing, Alg. 2: waiting time ----
   uint32_t nhu[N];
-  int64_t W[N];
+  tm_t W[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     nhu[t] = (uint32_t)__popcll(hm[t]);
@@ -309,7 +316,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
     int rounds = 0;
     while (true) {
       int gmax, g2;
-      int64_t top, w2;
+      tm_t top, w2;
       lane_top2(W, actm, gmax, top, g2, w2);
       if (gmax < 0) break;
       const bool has2 = g2 >= 0;
@@ -338,29 +345,29 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       int u = 0;
       while (!m_empty(cands)) {
         u = m_pop_low(cands);
-        int64_t trial;
+        tm_t trial;
         if (nhx == 0) {
-          trial = kInfT;
+          trial = kTInf;
         } else {
           const int s = u > topx ? u : topx;
           const uint32_t ld = ldx + V.su_fill[u];
           const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
-          trial = (int64_t)rt - (int64_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
+          trial = (tm_t)rt - (tm_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
         }
         if (!has2 || trial < w2 || m_empty(cands)) break;
       }
       const uint32_t fu = V.su_fill[u];
-      const int64_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
+      const tm_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
       // The two tours after the move, then the new times of every tour, kept
       // only if the maximum falls.
       const uint64_t ulo = u < 64 ? 1ull << u : 0ull, uhi = u < 64 ? 0ull : 1ull << (u - 64);
       const M128 smin_new{cands_all.lo & ~ulo, cands_all.hi & ~uhi}, smax_new{smx.lo | ulo, smx.hi | uhi};
       const uint32_t ldmin = lpick(load, gmin) - fu;
-      const int64_t Wmin1 = ((actm >> gmin) & 1u)
+      const tm_t Wmin1 = ((actm >> gmin) & 1u)
                                 ? lane_twait(V, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
                                 : Wmin0;
-      const int64_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, smax_new, ldx + fu, nhx, dmx) : Wmax0;
-      int64_t Wn[N];
+      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, smax_new, ldx + fu, nhx, dmx) : Wmax0;
+      tm_t Wn[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) Wn[t] = t == gmin ? Wmin1 : (t == gmax ? Wmax1 : W[t]);
       ++rounds;
@@ -381,8 +388,8 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
 #pragma unroll
   for (int t = 0; t < N; ++t) cost += (uint64_t)(__popcll(hm[t]) + m_pop(sm[t])) * (uint64_t)L[t];
   o.cost = cost;
-  o.makespan = tmax;
-  if (tmax == kInfT) o.flags |= kCandInfMakespan;
+  o.makespan = tmax == kTInf ? kInfT : (tmax == kTNegInf ? kNegInfT : (int64_t)tmax);
+  if (tmax == kTInf) o.flags |= kCandInfMakespan;
   return o;
 }
 
