@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // The same launch with one candidate per lane (lane_eval.h): for instances of
 // at most kLaneMaxTours tours, unless a flag asks for the segment version.
-template <int N, bool DLDS, int MODE>
+template <int N, bool SMALL, int MODE>
 __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t *__restrict__ moves,
                                                    uint32_t n, int64_t t_star_arg, uint64_t seed,
                                                    uint32_t inst_index, uint64_t *__restrict__ out_key,
@@ -96,11 +96,11 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
   if (run_flag && *run_flag == 0u) return;
   __shared__ LaneBase s_base;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
-  const uint32_t img_words = round4(P.lay.total_words);
   stage(lds, P.image, P.lay.total_words);
-  if (DLDS) stage(lds + img_words, P.dist, (uint32_t)(P.V * P.V));
   __syncthreads();
-  const View V = make_view(lds, P.lay, DLDS ? lds + img_words : P.dist);
+  // The distance matrix stays in global memory: a candidate reads at most a
+  // few legs of it.
+  const View V = make_view(lds, P.lay, P.dist);
   if (threadIdx.x < N) {
     const int t = threadIdx.x;
     uint32_t R = 0, ld = 0;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
     if (!m.valid) {
       r.flags = kCandInvalid;
     } else {
-      const LaneOut o = eval_lane<N>(V, P, s_base, m);
+      const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m);
       r.flags = o.flags;
       if (o.feasible) {
         r.cost_km = (float)((double)o.cost / 1000.0);
@@ -643,11 +643,15 @@ hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, ui
 
 // The instantiation for the instance: distance matrix in LDS or not, full
 // walk or delta evaluation.
-template <int MODE, bool DLDS, class... A>
-hipError_t launch_lane(const InstParams &P, int grid, size_t lds, hipStream_t s, A... a) {
+size_t lane_lds_bytes(const InstParams &P) { return (size_t)round4(P.lay.total_words) * 4; }
+bool lane_small(const InstParams &P) { return P.NHU <= 32 && P.NSU <= 64; }
+
+template <int MODE, bool SMALL, class... A>
+hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
+  const size_t lds = lane_lds_bytes(P);
   switch (P.NT) {
 #define BL_LANE_CASE(N) \
-    case N: hipLaunchKernelGGL((k_eval_lane<N, DLDS, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
+    case N: hipLaunchKernelGGL((k_eval_lane<N, SMALL, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
     BL_LANE_CASE(1) BL_LANE_CASE(2) BL_LANE_CASE(3) BL_LANE_CASE(4)
     BL_LANE_CASE(5) BL_LANE_CASE(6) BL_LANE_CASE(7) BL_LANE_CASE(8)
 #undef BL_LANE_CASE
@@ -660,7 +664,7 @@ template <int MODE, class... A>
 hipError_t launch_k_eval(const InstParams &P, int grid, hipStream_t s, A... a) {
   const size_t lds = eval_lds_bytes(P);
   if (lane_eval_on(P))
-    return P.d_in_lds ? launch_lane<MODE, true>(P, grid, lds, s, a...) : launch_lane<MODE, false>(P, grid, lds, s, a...);
+    return lane_small(P) ? launch_lane<MODE, true>(P, grid, s, a...) : launch_lane<MODE, false>(P, grid, s, a...);
   const bool walk = (P.flags & kFullWalk) != 0;
   if (P.d_in_lds) {
     if (walk)
@@ -725,13 +729,13 @@ bool lane_eval_on(const InstParams &P) {
   return P.narrow && P.NT >= 1 && P.NT <= kLaneMaxTours && !(P.flags & (kFullWalk | kWideKeys | kSegmentEval));
 }
 
-template <bool DLDS, int MODE>
+template <bool SMALL, int MODE>
 int lane_occupancy(const InstParams &P, size_t lds) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (P.NT) {
 #define BL_LANE_OCC(N) \
-    case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_lane<N, DLDS, MODE>, 256, lds); break;
+    case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_lane<N, SMALL, MODE>, 256, lds); break;
     BL_LANE_OCC(1) BL_LANE_OCC(2) BL_LANE_OCC(3) BL_LANE_OCC(4)
     BL_LANE_OCC(5) BL_LANE_OCC(6) BL_LANE_OCC(7) BL_LANE_OCC(8)
 #undef BL_LANE_OCC
@@ -744,8 +748,9 @@ int eval_occupancy(const InstParams &P, bool search) {
   int nb = 0;
   const size_t lds = eval_lds_bytes(P);
   if (lane_eval_on(P)) {
-    if (P.d_in_lds) return search ? lane_occupancy<true, kModeSearch>(P, lds) : lane_occupancy<true, kModeBatch>(P, lds);
-    return search ? lane_occupancy<false, kModeSearch>(P, lds) : lane_occupancy<false, kModeBatch>(P, lds);
+    const size_t ll = lane_lds_bytes(P);
+    if (lane_small(P)) return search ? lane_occupancy<true, kModeSearch>(P, ll) : lane_occupancy<true, kModeBatch>(P, ll);
+    return search ? lane_occupancy<false, kModeSearch>(P, ll) : lane_occupancy<false, kModeBatch>(P, ll);
   }
   hipError_t e;
   const bool walk = (P.flags & kFullWalk) != 0;

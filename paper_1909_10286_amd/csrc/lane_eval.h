@@ -7,6 +7,8 @@
 // results are the segment version's, which the tests compare it with.
 #pragma once
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace bl {
@@ -43,7 +45,10 @@ template <int N, class T>
 __device__ __forceinline__ T lpick(const T (&a)[N], int i) {
   T r = lopaque(a[0]);
 #pragma unroll
-  for (int k = 1; k < N; ++k) r = i == k ? lopaque(a[k]) : r;
+  for (int k = 1; k < N; ++k) {
+    const T ak = lopaque(a[k]);  // outside the select: no branch around it
+    r = i == k ? ak : r;
+  }
   return r;
 }
 
@@ -186,9 +191,18 @@ struct LaneOut {
   bool feasible;
 };
 
-template <int N>
+__device__ __forceinline__ int lane_popc(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ int lane_popc(uint64_t x) { return __popcll((unsigned long long)x); }
+__device__ __forceinline__ int lane_ffs(uint32_t x) { return __ffs(x); }
+__device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned long long)x); }
+
+// SMALL: at most 32 HUs and 64 SUs, so that an HU mask is one 32-bit word
+// and an SU mask one 64-bit word (the high half of M128 stays zero, which
+// the compiler folds away).
+template <int N, bool SMALL>
 __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
                                              const Move &m) {
+  using HM = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
   LaneOut o;
   o.flags = 0;
   const Nbrs nb = move_nbrs(V, m);
@@ -233,13 +247,13 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
     if (nf > 0) actm |= 1u << t;
     shsum += sh;
   }
-  uint64_t hm[N];
+  HM hm[N];
   M128 sm[N];
   uint32_t R[N], load[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    hm[t] = V.hu_mask[t];
-    sm[t] = M128{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
+    hm[t] = (HM)V.hu_mask[t];
+    sm[t] = M128{V.su_mask[2 * t], SMALL ? 0ull : V.su_mask[2 * t + 1]};
     R[t] = B.R[t];
     load[t] = B.load[t];
   }
@@ -270,18 +284,18 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         o.flags |= kCandCapHu;
         break;
       }
-      uint64_t cands = lpick(hm, gmin);
+      HM cands = lpick(hm, gmin);
       const uint32_t lcx = lpick(lc, gmax);
       const uint32_t ax = lpick(A, gmax), rx = lpick(R, gmax);
       int u = 0;
       while (cands) {
-        u = __ffsll((unsigned long long)cands) - 1;
+        u = lane_ffs(cands) - 1;
         cands &= cands - 1;
         const tm_t trial = (tm_t)(lcx + (uint32_t)udiv(3600ull * ax, rx + V.hu_rate[u]));
         if (!has2 || trial < t2 || cands == 0) break;
       }
       const uint32_t ru = V.hu_rate[u];
-      const uint64_t bit = 1ull << u;
+      const HM bit = (HM)1 << u;
       const tm_t Tmin0 = lpick(T, gmin), Tmax0 = lpick(T, gmax);
       // The two tours that change, recomputed (inactive tours keep their value).
       const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
@@ -309,7 +323,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   tm_t W[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    nhu[t] = (uint32_t)__popcll(hm[t]);
+    nhu[t] = (uint32_t)lane_popc(hm[t]);
     W[t] = ((actm >> t) & 1u) ? lane_twait(V, sm[t], load[t], nhu[t], dm[t]) : 0;
   }
   if (embedded) {
@@ -360,7 +374,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const tm_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
       // The two tours after the move, then the new times of every tour, kept
       // only if the maximum falls.
-      const uint64_t ulo = u < 64 ? 1ull << u : 0ull, uhi = u < 64 ? 0ull : 1ull << (u - 64);
+      const uint64_t ulo = (SMALL || u < 64) ? 1ull << u : 0ull, uhi = (SMALL || u < 64) ? 0ull : 1ull << (u - 64);
       const M128 smin_new{cands_all.lo & ~ulo, cands_all.hi & ~uhi}, smax_new{smx.lo | ulo, smx.hi | uhi};
       const uint32_t ldmin = lpick(load, gmin) - fu;
       const tm_t Wmin1 = ((actm >> gmin) & 1u)
@@ -386,7 +400,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   // ---- path length (sec. 2.2) ----
   uint64_t cost = shsum;
 #pragma unroll
-  for (int t = 0; t < N; ++t) cost += (uint64_t)(__popcll(hm[t]) + m_pop(sm[t])) * (uint64_t)L[t];
+  for (int t = 0; t < N; ++t) cost += (uint64_t)(lane_popc(hm[t]) + m_pop(sm[t])) * (uint64_t)L[t];
   o.cost = cost;
   o.makespan = tmax == kTInf ? kInfT : (tmax == kTNegInf ? kNegInfT : (int64_t)tmax);
   if (tmax == kTInf) o.flags |= kCandInfMakespan;
