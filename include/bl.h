@@ -59,7 +59,7 @@ typedef int32_t bl_status;
                                  results; implies BL_SEGMENT_EVAL) */
 #define BL_SEGMENT_EVAL 64u   /* evaluate each candidate on a segment of lanes, one
                                  tour per lane, also where the instance has at most
-                                 8 tours and one lane per candidate (all its tours in
+                                 12 tours and one lane per candidate (all its tours in
                                  registers) is the default (same results) */
 
 /* Per-candidate flags written by bl_evaluate_batch. */

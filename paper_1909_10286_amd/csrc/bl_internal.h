@@ -146,7 +146,7 @@ hipError_t launch_commit(const InstParams &P, int mode, uint64_t seed, uint32_t 
 hipError_t launch_select(const uint64_t *keys, uint32_t n, uint64_t *out, hipStream_t s);
 size_t eval_lds_bytes(const InstParams &P);
 // Whether the evaluation launches take one candidate per lane (instances of
-// at most 8 tours, unless a flag asks for the segment version).
+// at most 12 tours, unless a flag asks for the segment version).
 bool lane_eval_on(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);

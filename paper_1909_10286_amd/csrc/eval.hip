@@ -654,6 +654,7 @@ hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
     case N: hipLaunchKernelGGL((k_eval_lane<N, SMALL, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
     BL_LANE_CASE(1) BL_LANE_CASE(2) BL_LANE_CASE(3) BL_LANE_CASE(4)
     BL_LANE_CASE(5) BL_LANE_CASE(6) BL_LANE_CASE(7) BL_LANE_CASE(8)
+    BL_LANE_CASE(9) BL_LANE_CASE(10) BL_LANE_CASE(11) BL_LANE_CASE(12)
 #undef BL_LANE_CASE
     default: return hipErrorInvalidValue;
   }
@@ -738,6 +739,7 @@ int lane_occupancy(const InstParams &P, size_t lds) {
     case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_lane<N, SMALL, MODE>, 256, lds); break;
     BL_LANE_OCC(1) BL_LANE_OCC(2) BL_LANE_OCC(3) BL_LANE_OCC(4)
     BL_LANE_OCC(5) BL_LANE_OCC(6) BL_LANE_OCC(7) BL_LANE_OCC(8)
+    BL_LANE_OCC(9) BL_LANE_OCC(10) BL_LANE_OCC(11) BL_LANE_OCC(12)
 #undef BL_LANE_OCC
     default: break;
   }

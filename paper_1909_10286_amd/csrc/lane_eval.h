@@ -15,7 +15,7 @@ namespace bl {
 
 namespace {
 
-constexpr int kLaneMaxTours = 8;
+constexpr int kLaneMaxTours = 12;
 
 // Times in the rounds: 32-bit, which the instance's time bounds allow (the
 // lane version runs only on instances whose completion and waiting times

@@ -189,7 +189,7 @@ def test_evaluate_batch_parity(ctx, name, n, kind, flags, caps, tk):
                                        ("mid100", "emptybp"), ("tiny12", "inactive")])
 def test_delta_equals_full_walk(ctx, name, kind):
     """The default evaluation (base aggregates plus the legs a move changes;
-    one candidate per lane up to 8 tours, else 32-bit rebalancing keys on a
+    one candidate per lane up to 12 tours, else 32-bit rebalancing keys on a
     segment of lanes), the segment version, the full walk and the 64-bit keys
     agree bit for bit on 2^16 generated moves."""
     _say("delta vs walk", name, kind)
