@@ -39,8 +39,11 @@ DESCR = {
 
 
 HBM_PEAK_GBS = 8000.0
+# Instances of at most this many tours are evaluated one candidate per lane
+# (k_eval_lane), larger ones on a segment of lanes per candidate (k_eval).
+LANE_MAX_TOURS = 12
 KERNEL_SOURCES = ("paper_1909_10286_amd/csrc/eval.hip", "paper_1909_10286_amd/csrc/device.h",
-                  "paper_1909_10286_amd/csrc/bl_internal.h")
+                  "paper_1909_10286_amd/csrc/lane_eval.h", "paper_1909_10286_amd/csrc/bl_internal.h")
 
 
 def kernel_source_digest():
@@ -523,7 +526,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
                      "frac": alu / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "k_eval (search mode)", "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
+                     "kernel": ("k_eval_lane" if inst.n_tours <= LANE_MAX_TOURS else "k_eval") + " (search mode)",
+                     "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
                      "kernel_ms_per_launch": per_launch_s * 1e3,
                      "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                              "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc,
