@@ -110,6 +110,7 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
     s_base.R[t] = R;
     s_base.load[t] = ld;
   }
+  for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) s_base.rcp[k] = k ? 1.0 / (double)k : 0.0;
   __syncthreads();
   uint32_t it = 0;
   int64_t t_star = t_star_arg;

@@ -30,6 +30,7 @@ constexpr tm_t kTInf = INT32_MAX, kTNegInf = INT32_MIN;
 struct LaneBase {
   uint32_t R[kLaneMaxTours];
   uint32_t load[kLaneMaxTours];
+  double rcp[kMaxHus + 1];   // rcp[k] = 1/k (k >= 1): the reciprocals udiv_small takes
 };
 
 // The value in a VGPR as far as the optimiser knows, so that a select
@@ -127,11 +128,11 @@ __device__ __forceinline__ tm_t lane_tcompl(uint32_t lc, uint32_t A, uint32_t ra
   return rate == 0 ? kTInf : (tm_t)(lc + (uint32_t)udiv(3600ull * A, rate));
 }
 
-__device__ __forceinline__ tm_t lane_twait(const View &V, const M128 &msk, uint32_t ld, uint32_t nhu,
-                                           uint32_t dm) {
+__device__ __forceinline__ tm_t lane_twait(const View &V, const LaneBase &B, const M128 &msk, uint32_t ld,
+                                           uint32_t nhu, uint32_t dm) {
   if (m_empty(msk) || nhu == 0) return kTInf;
   const int s = m_top(msk);
-  const double r = 1.0 / (double)nhu;
+  const double r = B.rcp[nhu];
   return (tm_t)udiv(7200ull * dm, V.su_speed[s]) - (tm_t)udiv_small(ld - V.su_fill[s], nhu, r);
 }
 
@@ -324,7 +325,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     nhu[t] = (uint32_t)lane_popc(hm[t]);
-    W[t] = ((actm >> t) & 1u) ? lane_twait(V, sm[t], load[t], nhu[t], dm[t]) : 0;
+    W[t] = ((actm >> t) & 1u) ? lane_twait(V, B, sm[t], load[t], nhu[t], dm[t]) : 0;
   }
   if (embedded) {
     int rounds = 0;
@@ -355,7 +356,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const int topx = m_empty(smx) ? -1 : m_top(smx);
       const uint32_t ldx = lpick(load, gmax), nhx = lpick(nhu, gmax), dmx = lpick(dm, gmax);
       const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
-      const double r_nhx = nhx ? 1.0 / (double)nhx : 0.0;
+      const double r_nhx = B.rcp[nhx];
       int u = 0;
       while (!m_empty(cands)) {
         u = m_pop_low(cands);
@@ -378,9 +379,9 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const M128 smin_new{cands_all.lo & ~ulo, cands_all.hi & ~uhi}, smax_new{smx.lo | ulo, smx.hi | uhi};
       const uint32_t ldmin = lpick(load, gmin) - fu;
       const tm_t Wmin1 = ((actm >> gmin) & 1u)
-                                ? lane_twait(V, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
+                                ? lane_twait(V, B, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
                                 : Wmin0;
-      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, smax_new, ldx + fu, nhx, dmx) : Wmax0;
+      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, B, smax_new, ldx + fu, nhx, dmx) : Wmax0;
       tm_t Wn[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) Wn[t] = t == gmin ? Wmin1 : (t == gmax ? Wmax1 : W[t]);
