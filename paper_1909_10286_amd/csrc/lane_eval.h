@@ -289,10 +289,11 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const uint32_t lcx = lpick(lc, gmax);
       const uint32_t ax = lpick(A, gmax), rx = lpick(R, gmax);
       int u = 0;
+      tm_t trial = 0;   // g_max's completion time with the unit tried last
       while (cands) {
         u = lane_ffs(cands) - 1;
         cands &= cands - 1;
-        const tm_t trial = (tm_t)(lcx + (uint32_t)udiv(3600ull * ax, rx + V.hu_rate[u]));
+        trial = (tm_t)(lcx + (uint32_t)udiv(3600ull * ax, rx + V.hu_rate[u]));
         if (!has2 || trial < t2 || cands == 0) break;
       }
       const uint32_t ru = V.hu_rate[u];
@@ -301,7 +302,8 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       // The two tours that change, recomputed (inactive tours keep their value).
       const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
       const tm_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
-      const tm_t Tmax1 = ((actm >> gmax) & 1u) ? lane_tcompl(lcx, ax, Rmax) : Tmax0;
+      // g_max's new time is the trial of the unit moved (rates are positive).
+      const tm_t Tmax1 = ((actm >> gmax) & 1u) ? trial : Tmax0;
       // The new times of every tour, kept only if the maximum falls.
       tm_t Tn[N];
 #pragma unroll
@@ -358,9 +360,9 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
       const double r_nhx = B.rcp[nhx];
       int u = 0;
+      tm_t trial = kTInf;   // g_max's waiting time with the unit tried last
       while (!m_empty(cands)) {
         u = m_pop_low(cands);
-        tm_t trial;
         if (nhx == 0) {
           trial = kTInf;
         } else {
@@ -381,7 +383,9 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       const tm_t Wmin1 = ((actm >> gmin) & 1u)
                                 ? lane_twait(V, B, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
                                 : Wmin0;
-      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? lane_twait(V, B, smax_new, ldx + fu, nhx, dmx) : Wmax0;
+      // g_max's new time is the trial of the unit moved: its critical SU is
+      // the larger of the two, its load and HU count as in the trial.
+      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? trial : Wmax0;
       tm_t Wn[N];
 #pragma unroll
       for (int t = 0; t < N; ++t) Wn[t] = t == gmin ? Wmin1 : (t == gmax ? Wmax1 : W[t]);
