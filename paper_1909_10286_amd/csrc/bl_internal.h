@@ -12,6 +12,9 @@ constexpr int kMaxTours = 64;
 constexpr int kMaxHus = 64;
 constexpr int kMaxSus = 128;
 constexpr uint32_t kMaxCand = 1u << 24;
+// Room for candidates whose long rebalancing tails an evaluation launch
+// moves to its second pass; the ones beyond it finish in the first.
+constexpr uint32_t kDeferCap = 1u << 20;
 
 constexpr uint64_t kInfKey = ~0ull;
 constexpr int64_t kInfT = INT64_MAX;
@@ -107,6 +110,9 @@ struct InstParams {
   TraceRow *trace;
   uint32_t trace_cap;
   uint64_t *best_key;  // per-instance argmin slot
+  uint32_t *defer;     // [defer_cap] candidates whose SU rounds an evaluation launch left for its second pass
+  uint32_t *defer_cnt; // their count
+  uint32_t defer_cap;  // 0: no deferral
   uint16_t *hu_id;     // rank -> HU id
   uint16_t *su_id;     // rank -> SU id
 };

@@ -84,8 +84,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // The same launch with one candidate per lane (lane_eval.h): for instances of
 // at most kLaneMaxTours tours, unless a flag asks for the segment version.
+// phase 0: candidates 0 .. n-1; one whose SU rounds go past kSuDefer rounds
+// is appended to the instance's deferred list (while it has room) instead of
+// holding its wave in a long tail of rounds.  phase 1: the deferred
+// candidates, densely, with no limit.
+constexpr int kSuDefer = 2;
+
 template <int N, bool SMALL, int MODE>
-__global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t *__restrict__ moves,
+__global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, const uint64_t *__restrict__ moves,
                                                    uint32_t n, int64_t t_star_arg, uint64_t seed,
                                                    uint32_t inst_index, uint64_t *__restrict__ out_key,
                                                    float *__restrict__ out_cost,
@@ -94,6 +100,8 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
                                                    const uint32_t *__restrict__ gather,
                                                    const uint32_t *__restrict__ run_flag) {
   if (run_flag && *run_flag == 0u) return;
+  const uint32_t total = phase == 0 ? n : *P.defer_cnt;
+  if (phase == 1 && blockIdx.x * blockDim.x >= total) return;
   __shared__ LaneBase s_base;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   stage(lds, P.image, P.lay.total_words);
@@ -118,9 +126,11 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
     it = P.st->it;
     t_star = P.st->t_best;
   }
+  const int su_limit = phase == 0 && P.defer_cap ? kSuDefer : 0;
   uint64_t best = kInfKey;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const uint32_t c = phase == 0 ? i : P.defer[i];
     const uint32_t ci = MODE == kModeGather ? gather[c] : c;
     const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
     const Move m = decode_move(w, V, P);
@@ -128,7 +138,15 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
     if (!m.valid) {
       r.flags = kCandInvalid;
     } else {
-      const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m);
+      LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, su_limit);
+      if (o.deferred) {
+        const uint32_t slot = atomicAdd(P.defer_cnt, 1u);
+        if (slot < P.defer_cap) {
+          P.defer[slot] = c;
+          continue;
+        }
+        o = eval_lane<N, SMALL>(V, P, s_base, m, 0);   // no room: finish here
+      }
       r.flags = o.flags;
       if (o.feasible) {
         r.cost_km = (float)((double)o.cost / 1000.0);
@@ -149,6 +167,8 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, const uint64_t 
   }
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 // Base preparation: optional eq. (6) pick (copy x* or x_old to the base
 // slot), then the base view written into the instance image.  Run by one
@@ -648,11 +668,11 @@ size_t lane_lds_bytes(const InstParams &P) { return (size_t)round4(P.lay.total_w
 bool lane_small(const InstParams &P) { return P.NHU <= 32 && P.NSU <= 64; }
 
 template <int MODE, bool SMALL, class... A>
-hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
+hipError_t launch_lane_phase(const InstParams &P, int phase, int grid, hipStream_t s, A... a) {
   const size_t lds = lane_lds_bytes(P);
   switch (P.NT) {
 #define BL_LANE_CASE(N) \
-    case N: hipLaunchKernelGGL((k_eval_lane<N, SMALL, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
+    case N: hipLaunchKernelGGL((k_eval_lane<N, SMALL, MODE>), dim3(grid), dim3(256), lds, s, P, phase, a...); break;
     BL_LANE_CASE(1) BL_LANE_CASE(2) BL_LANE_CASE(3) BL_LANE_CASE(4)
     BL_LANE_CASE(5) BL_LANE_CASE(6) BL_LANE_CASE(7) BL_LANE_CASE(8)
     BL_LANE_CASE(9) BL_LANE_CASE(10) BL_LANE_CASE(11) BL_LANE_CASE(12)
@@ -660,6 +680,16 @@ hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The two phases of one evaluation launch, the deferred list emptied first
+// (by a kernel, so that the sequence can be captured in a graph).
+template <int MODE, bool SMALL, class... A>
+hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
+  if (P.defer_cap) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, P.defer_cnt, 0u);
+  hipError_t e = launch_lane_phase<MODE, SMALL>(P, 0, grid, s, a...);
+  if (e != hipSuccess || !P.defer_cap) return e;
+  return launch_lane_phase<MODE, SMALL>(P, 1, grid, s, a...);
 }
 
 template <int MODE, class... A>

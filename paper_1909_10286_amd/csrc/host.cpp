@@ -39,7 +39,8 @@ struct Instance {
   uint16_t *d_sol = nullptr, *d_units = nullptr;
   SearchState *d_st = nullptr;
   TraceRow *d_trace = nullptr;
-  uint64_t *d_best = nullptr;
+  uint64_t *d_best = nullptr;   // argmin slot (8 B), then the deferred-candidate count (4 B)
+  uint32_t *d_defer = nullptr;  // deferred-candidate list of the one-candidate-per-lane launches
   bool base_ready = false, started = false;
   int occ_batch = 1, occ_search = 1;
 };
@@ -150,6 +151,7 @@ void free_instance(Instance *I) {
   (void)hipFree(I->d_st);
   (void)hipFree(I->d_trace);
   (void)hipFree(I->d_best);
+  (void)hipFree(I->d_defer);
 }
 
 // Solution slot layout inside one u16 buffer.
@@ -677,6 +679,15 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   P.hu_id = R->d_units;
   P.su_id = R->d_units + NHU;
   if (eval_lds_bytes(P) > 160 * 1024) return cleanup(fail(c, BL_EINVAL, "instance image exceeds LDS"));
+  P.defer = nullptr;
+  P.defer_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(R->d_best) + 8);
+  P.defer_cap = 0;
+  if (lane_eval_on(P)) {
+    if ((e = hipMalloc(&R->d_defer, (size_t)kDeferCap * 4)) != hipSuccess)
+      return cleanup(hip_fail(c, e, "hipMalloc deferred list"));
+    P.defer = R->d_defer;
+    P.defer_cap = kDeferCap;
+  }
   R->occ_batch = eval_occupancy(P, false);
   R->occ_search = eval_occupancy(P, true);
   c->inst.push_back(std::move(I));

@@ -190,6 +190,7 @@ struct LaneOut {
   int64_t makespan;
   uint32_t flags;
   bool feasible;
+  bool deferred;   // stopped before its SU rounds were done (see su_limit)
 };
 
 __device__ __forceinline__ int lane_popc(uint32_t x) { return __popc(x); }
@@ -201,11 +202,16 @@ __device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned l
 // and an SU mask one 64-bit word (the high half of M128 stays zero, which
 // the compiler folds away).
 template <int N, bool SMALL>
+//
+// su_limit > 0: when the SU rounds would go past su_limit rounds the
+// evaluation stops with `deferred` set and no result; the caller evaluates
+// the candidate again later with su_limit = 0 (no limit).
 __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
-                                             const Move &m) {
+                                             const Move &m, int su_limit) {
   using HM = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
   LaneOut o;
   o.flags = 0;
+  o.deferred = false;
   const Nbrs nb = move_nbrs(V, m);
   if (!delta_feasible(V, m)) {
     o.feasible = false;
@@ -346,6 +352,10 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
       if (rounds == (int)P.cap_su) {
         o.flags |= kCandCapSu;
         break;
+      }
+      if (su_limit > 0 && rounds == su_limit) {
+        o.deferred = true;
+        return o;
       }
       uint64_t slo[N], shi[N];
 #pragma unroll
