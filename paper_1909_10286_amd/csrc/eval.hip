@@ -100,7 +100,9 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, cons
                                                    const uint32_t *__restrict__ gather,
                                                    const uint32_t *__restrict__ run_flag) {
   if (run_flag && *run_flag == 0u) return;
-  const uint32_t total = phase == 0 ? n : *P.defer_cnt;
+  // The counter goes on counting past the list's room (those candidates
+  // finish in the first pass), so the second pass takes at most defer_cap.
+  const uint32_t total = phase == 0 ? n : min(*P.defer_cnt, P.defer_cap);
   if (phase == 1 && blockIdx.x * blockDim.x >= total) return;
   __shared__ LaneBase s_base;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);

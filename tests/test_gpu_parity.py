@@ -213,6 +213,32 @@ def test_delta_equals_full_walk(ctx, name, kind):
     assert (ga[3] & bl.CAND_INFEASIBLE).any()
 
 
+@pytest.mark.parametrize("name", ["mid100", "clust500"])
+def test_deferred_list_overflow(ctx, name):
+    """A batch of 2^21 copies of a move whose SU rebalancing runs several
+    rounds: the evaluation's second pass takes the first 2^20 deferred
+    candidates, the rest finish in the first pass, and every copy gets the
+    oracle's result (with its own index in the key)."""
+    _say("deferred overflow", name)
+    inst = _instance(name)
+    base = _walk_base(inst, OI.init_solution(inst), 5, 40)
+    iid = _setup(ctx, inst, base)
+    words = oracle_words(inst, base, 42, 3, 600)
+    best_w, best_r = None, 0
+    for i, w in enumerate(words):
+        r = S.evaluate_move(inst, base, MV.decode(int(w)), i, M.GATE_LE, 1 << 40)
+        if r.evaluation is not None and r.evaluation.feasible and r.evaluation.su_rounds > best_r:
+            best_w, best_r = w, r.evaluation.su_rounds
+    assert best_r >= 4, "no move with a long SU tail in the sample"
+    n = 1 << 21
+    gk, gc, gm, gf = _gpu_eval(ctx, iid, np.full(n, best_w, np.uint64), 1 << 40)
+    ok, oc, om, of = oracle_batch(inst, base, np.array([best_w], np.uint64), 1 << 40)
+    assert np.array_equal(gk >> np.uint64(24), np.full(n, ok[0] >> np.uint64(24), np.uint64))
+    assert np.array_equal(gk & np.uint64((1 << 24) - 1), np.arange(n, dtype=np.uint64))
+    assert (gm == om[0]).all() and (gf == of[0]).all()
+    assert np.allclose(gc, oc[0], rtol=1e-5)
+
+
 def test_evaluate_invalid_and_ragged(ctx):
     _say("evaluate invalid")
     inst = _instance("tiny12")
