@@ -39,8 +39,9 @@ DESCR = {
 
 
 HBM_PEAK_GBS = 8000.0
-# Instances of at most this many tours are evaluated one candidate per lane
-# (k_eval_lane), larger ones on a segment of lanes per candidate (k_eval).
+# Instances (and batches whose members all have) at most this many tours are
+# evaluated one candidate per lane (k_eval_lane, k_eval_multi_lane), larger
+# ones on a segment of lanes per candidate (k_eval, k_eval_multi).
 LANE_MAX_TOURS = 12
 KERNEL_SOURCES = ("paper_1909_10286_amd/csrc/eval.hip", "paper_1909_10286_amd/csrc/device.h",
                   "paper_1909_10286_amd/csrc/lane_eval.h", "paper_1909_10286_amd/csrc/bl_internal.h")
@@ -184,7 +185,8 @@ def bench_batch(a):
                    "parallelism": "single GPU"},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / LDS_PEAK_GBS, "traffic": None,
-                     "kernel": "k_eval_multi", "kernel_ms_per_launch": per_launch_s * 1e3},
+                     "kernel": "k_eval_multi_lane" if max(i.n_tours for i in insts) <= LANE_MAX_TOURS
+                     else "k_eval_multi", "kernel_ms_per_launch": per_launch_s * 1e3},
     }
     ctx.close()
     print(json.dumps(out), flush=True)

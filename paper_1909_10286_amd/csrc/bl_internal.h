@@ -131,6 +131,8 @@ struct BatchParams {
   const uint32_t *tile;      // [K] candidates per item, by member
   uint32_t *queue;           // [1] next item to pop
   uint32_t walk;             // some member asks for the full walk (host side)
+  uint32_t lane_n;           // > 0: one candidate per lane with this many tour slots (host side)
+  uint32_t lane_small;       // every member has at most 32 HUs and 64 SUs (host side)
 };
 
 // Kernel entry points (launch wrappers defined in eval.hip).
@@ -156,7 +158,10 @@ size_t eval_lds_bytes(const InstParams &P);
 bool lane_eval_on(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);
-int batch_occupancy(size_t lds, bool walk);
+int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small);
+// Tour slots of the one-candidate-per-lane batched kernel for members of at
+// most max_nt tours (4, 8 or 12), 0 beyond 12.
+int batch_lane_tours(int max_nt);
 hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s);
 hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s);
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s);

@@ -84,11 +84,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // The same launch with one candidate per lane (lane_eval.h): for instances of
 // at most kLaneMaxTours tours, unless a flag asks for the segment version.
-// phase 0: candidates 0 .. n-1; one whose SU rounds go past kSuDefer rounds
-// is appended to the instance's deferred list (while it has room) instead of
-// holding its wave in a long tail of rounds.  phase 1: the deferred
-// candidates, densely, with no limit.
-constexpr int kSuDefer = 2;
+// phase 0: candidates 0 .. n-1; one whose SU rounds go past su_defer_rounds(N)
+// rounds is appended to the instance's deferred list (while it has room)
+// instead of holding its wave in a long tail of rounds.  phase 1: the
+// deferred candidates, densely, with no limit.  A deferred candidate is
+// evaluated again from the start, so the limit trades that repeated work
+// against the tail; rounds cost more with more tours, and the tails grow
+// longer.  Measured: 3 rounds is fastest at 5 tours (of 1, 2, 3), 1 round at
+// 10 tours.
+constexpr int su_defer_rounds(int n_tours) { return n_tours <= 6 ? 3 : 1; }
 
 template <int N, bool SMALL, int MODE>
 __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, const uint64_t *__restrict__ moves,
@@ -111,16 +115,7 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, cons
   // The distance matrix stays in global memory: a candidate reads at most a
   // few legs of it.
   const View V = make_view(lds, P.lay, P.dist);
-  if (threadIdx.x < N) {
-    const int t = threadIdx.x;
-    uint32_t R = 0, ld = 0;
-    for (uint64_t mm = V.hu_mask[t]; mm; mm &= mm - 1) R += V.hu_rate[__ffsll((unsigned long long)mm) - 1];
-    M128 sm{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
-    while (!m_empty(sm)) ld += V.su_fill[m_pop_low(sm)];
-    s_base.R[t] = R;
-    s_base.load[t] = ld;
-  }
-  for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) s_base.rcp[k] = k ? 1.0 / (double)k : 0.0;
+  lane_base_fill(s_base, V, N);
   __syncthreads();
   uint32_t it = 0;
   int64_t t_star = t_star_arg;
@@ -128,7 +123,7 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, cons
     it = P.st->it;
     t_star = P.st->t_best;
   }
-  const int su_limit = phase == 0 && P.defer_cap ? kSuDefer : 0;
+  const int su_limit = phase == 0 && P.defer_cap ? su_defer_rounds(N) : 0;
   uint64_t best = kInfKey;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
@@ -594,6 +589,58 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
   commit_body(P, V, mode, B.seed, B.index_base + k);
 }
 
+// The batched evaluation with one candidate per lane, for batches whose
+// members all have at most N tours and 32-bit time bounds: a member's tours
+// beyond its own count are empty and inactive (eval_lane's nt), so one
+// instantiation serves members of any smaller tour count.
+template <int N, bool SMALL>
+__global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
+  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
+  __shared__ uint32_t s_item;
+  __shared__ LaneBase s_base;
+  int cur = -1;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(B.queue, 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads below
+    if (item >= B.total_items) break;
+    int lo = 0, hi = (int)B.K;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (B.item_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    const uint32_t k = B.order[lo];
+    const InstParams &P = B.inst[k];
+    const View V = make_view(lds, P.lay, P.dist);
+    if ((int)k != cur) {   // uniform over the workgroup
+      stage(lds, P.image, P.lay.total_words);
+      __syncthreads();
+      lane_base_fill(s_base, V, P.NT);
+      cur = (int)k;
+    }
+    __syncthreads();
+    const uint32_t tile = B.tile[k];
+    const uint32_t c0 = (item - B.item_off[lo]) * tile;
+    const uint32_t c1 = c0 + tile < B.n ? c0 + tile : B.n;
+    const uint32_t it = P.st->it;
+    const int64_t t_star = P.st->t_best;
+    const uint32_t idx = B.index_base + k;
+    const int nt = P.NT;
+    uint64_t best = kInfKey;
+    for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
+      if (!m.valid) continue;
+      const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);
+      if (o.feasible && !is_gated(o.makespan, t_star, P.flags)) {
+        const uint64_t key = (o.cost << 24) | (uint64_t)c;
+        best = key < best ? key : best;
+      }
+    }
+    wave_min_to(best, P.best_key);
+    __syncthreads();
+  }
+}
+
 template <bool WALK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_multi(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
@@ -804,12 +851,27 @@ int eval_occupancy(const InstParams &P, bool search) {
 
 size_t batch_lds_bytes(uint32_t max_image_words) { return (size_t)round4(max_image_words) * 4; }
 
-int batch_occupancy(size_t lds, bool walk) {
+template <int N, bool SMALL>
+int multi_lane_occupancy(size_t lds) {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi_lane<N, SMALL>, 256, lds);
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small) {
+  switch (lane_n) {
+    case 4: return lane_small ? multi_lane_occupancy<4, true>(lds) : multi_lane_occupancy<4, false>(lds);
+    case 8: return lane_small ? multi_lane_occupancy<8, true>(lds) : multi_lane_occupancy<8, false>(lds);
+    case 12: return lane_small ? multi_lane_occupancy<12, true>(lds) : multi_lane_occupancy<12, false>(lds);
+    default: break;
+  }
   int nb = 0;
   const hipError_t e = walk ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi<true>, 256, lds)
                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi<false>, 256, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
+
+int batch_lane_tours(int max_nt) { return max_nt <= 4 ? 4 : (max_nt <= 8 ? 8 : (max_nt <= kLaneMaxTours ? 12 : 0)); }
 
 hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare_multi, dim3(B.K), dim3(256), 0, s, B, (int)kPrepFromBase);
@@ -819,6 +881,16 @@ hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s) {
 
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, B.queue);
+  switch (B.lane_n) {
+#define BL_MULTI_LANE(N) \
+    case N: \
+      if (B.lane_small) hipLaunchKernelGGL((k_eval_multi_lane<N, true>), dim3(grid), dim3(256), lds, s, B); \
+      else hipLaunchKernelGGL((k_eval_multi_lane<N, false>), dim3(grid), dim3(256), lds, s, B); \
+      return hipGetLastError();
+    BL_MULTI_LANE(4) BL_MULTI_LANE(8) BL_MULTI_LANE(12)
+#undef BL_MULTI_LANE
+    default: break;
+  }
   if (B.walk)
     hipLaunchKernelGGL(k_eval_multi<true>, dim3(grid), dim3(256), lds, s, B);
   else

@@ -68,6 +68,8 @@ struct Batch {
   size_t lds = 0;
   int occ = 1;
   bool walk = false;  // some member asks for the full walk
+  int lane_n = 0;     // > 0: one candidate per lane, this many tour slots
+  bool lane_small = false;
   bool started = false;
 };
 
@@ -305,6 +307,8 @@ BatchParams batch_params(const Batch &B, const bl_search_params *p) {
   bp.tile = B.d_sched + 2 * K + 1;
   bp.queue = B.d_sched + 3 * K + 1;
   bp.walk = B.walk ? 1u : 0u;
+  bp.lane_n = (uint32_t)B.lane_n;
+  bp.lane_small = B.lane_small ? 1u : 0u;
   return bp;
 }
 
@@ -341,6 +345,7 @@ std::string batch_signature(const bl_ctx *c, const Batch &B) {
     mix(I.NHU);
     mix(I.NSU);
   }
+  mix((uint64_t)B.lane_n);   // the kernel the schedule was timed with
   char buf[32];
   snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
   return buf;
@@ -922,11 +927,23 @@ bl_status bl_batch_create(bl_ctx *c, const int32_t *ids, int32_t n_inst, uint32_
     B->max_image_words = std::max(B->max_image_words, I->P.lay.total_words);
     if (I->P.flags & kFullWalk) B->walk = true;
   }
+  // One candidate per lane when every member allows it (lane_eval_on), with
+  // tour slots for the largest member; else one segment per candidate.
+  bool lane = true, small = true;
+  int max_nt = 0;
+  for (int32_t id : B->members) {
+    const InstParams &P = c->inst[id]->P;
+    lane = lane && lane_eval_on(P);
+    small = small && P.NHU <= 32 && P.NSU <= 64;
+    max_nt = std::max(max_nt, (int)P.NT);
+  }
+  B->lane_n = lane ? batch_lane_tours(max_nt) : 0;
+  B->lane_small = small;
   B->n = n_cand;
   B->lds = batch_lds_bytes(B->max_image_words);
   if (B->lds > 160 * 1024) return fail(c, BL_EINVAL, "member image exceeds LDS");
   HIP_TRY(c, hipSetDevice(c->device));
-  B->occ = batch_occupancy(B->lds, B->walk);
+  B->occ = batch_occupancy(B->lds, B->walk, B->lane_n, B->lane_small);
   const size_t K = B->members.size();
   HIP_TRY(c, hipMalloc(&B->d_inst, K * sizeof(InstParams)));
   if (hipMalloc(&B->d_sched, (3 * K + 2) * sizeof(uint32_t)) != hipSuccess) {

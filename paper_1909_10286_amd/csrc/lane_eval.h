@@ -33,6 +33,24 @@ struct LaneBase {
   double rcp[kMaxHus + 1];   // rcp[k] = 1/k (k >= 1): the reciprocals udiv_small takes
 };
 
+// Fills the per-tour sums of `B` for the tours 0..nt-1 of the base in V (zero
+// beyond), and the reciprocal table.  Called by a whole workgroup; the caller
+// synchronises before and after.
+__device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, int nt) {
+  if (threadIdx.x < kLaneMaxTours) {
+    const int t = threadIdx.x;
+    uint32_t R = 0, ld = 0;
+    if (t < nt) {
+      for (uint64_t mm = V.hu_mask[t]; mm; mm &= mm - 1) R += V.hu_rate[__ffsll((unsigned long long)mm) - 1];
+      M128 sm{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
+      while (!m_empty(sm)) ld += V.su_fill[m_pop_low(sm)];
+    }
+    B.R[t] = R;
+    B.load[t] = ld;
+  }
+  for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) B.rcp[k] = k ? 1.0 / (double)k : 0.0;
+}
+
 // The value in a VGPR as far as the optimiser knows, so that a select
 // chain over the tours stays a chain of selects instead of becoming an
 // indexed load from a stack copy of the array.
@@ -201,13 +219,17 @@ __device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned l
 // SMALL: at most 32 HUs and 64 SUs, so that an HU mask is one 32-bit word
 // and an SU mask one 64-bit word (the high half of M128 stays zero, which
 // the compiler folds away).
-template <int N, bool SMALL>
 //
 // su_limit > 0: when the SU rounds would go past su_limit rounds the
 // evaluation stops with `deferred` set and no result; the caller evaluates
 // the candidate again later with su_limit = 0 (no limit).
+//
+// nt: the instance's tour count, at most N.  Tours nt..N-1 are taken as
+// empty and inactive and as holding no units: they are then never g_max, g2
+// or a donor, add nothing to the cost, and the result is that of N = nt.
+template <int N, bool SMALL>
 __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
-                                             const Move &m, int su_limit) {
+                                             const Move &m, int su_limit, int nt = N) {
   using HM = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
   LaneOut o;
   o.flags = 0;
@@ -228,10 +250,11 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   uint64_t shsum = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    int64_t Lx = V.t_len[t];
-    uint32_t a = V.t_area[t], ms = V.t_msum[t], mc = V.t_mcnt[t];
-    uint64_t sh = V.t_sh[t];
-    int nf = (int)V.t_end[t] - (int)V.t_start[t];
+    const bool live = t < nt;
+    int64_t Lx = live ? V.t_len[t] : 0u;
+    uint32_t a = live ? V.t_area[t] : 0u, ms = live ? V.t_msum[t] : 0u, mc = live ? V.t_mcnt[t] : 0u;
+    uint64_t sh = live ? V.t_sh[t] : 0ull;
+    int nf = live ? (int)V.t_end[t] - (int)V.t_start[t] : 0;
     if (ch.any && t == ch.Ts) {
       Lx += ch.dLs;
       a -= ch.mv_area;
@@ -259,8 +282,9 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   uint32_t R[N], load[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    hm[t] = (HM)V.hu_mask[t];
-    sm[t] = M128{V.su_mask[2 * t], SMALL ? 0ull : V.su_mask[2 * t + 1]};
+    const bool live = t < nt;
+    hm[t] = live ? (HM)V.hu_mask[t] : (HM)0;
+    sm[t] = M128{live ? V.su_mask[2 * t] : 0ull, (SMALL || !live) ? 0ull : V.su_mask[2 * t + 1]};
     R[t] = B.R[t];
     load[t] = B.load[t];
   }

@@ -108,6 +108,39 @@ def test_batch_schedule_and_graph_do_not_change_results(ctx, tmp_path):
     assert again["result"] == first
 
 
+@pytest.mark.parametrize("ks", [
+    [0, 2, 4, 1, 6, 9],              # 2-4 tours: 4 tour slots, one-word masks
+    [0, 5, 10, 3, 11, 13],           # 2-8 tours: 8 tour slots
+    [0, 2, 4, 8, 10, 3, 11, 34],     # member 34 has 72 SUs: two-word SU masks
+])
+def test_batch_lane_equals_segment(ctx, ks):
+    """The batched kernel with one candidate per lane (a member's tours
+    beyond its own count left empty and inactive) and with one segment per
+    candidate (every member uploaded with BL_SEGMENT_EVAL) give the same
+    trajectories and best solutions."""
+    _say("batch lane vs segment", ks)
+    thr = S.eps_threshold(0.5)
+
+    def run(flags):
+        ids = []
+        for k in ks:
+            inst = inputs.make_batch_instance(k, accept=OI.init_feasible)
+            iid = ctx.instance_upload(inst, flags=flags)
+            ctx.solution_upload(iid, bl.SLOT_BASE, to_csr(OI.init_solution(inst)))
+            ids.append(iid)
+        b = ctx.batch_create(ids, 1 << 14)
+        ctx.batch_start(b, 12)
+        for _ in range(12):
+            ctx.batch_step(b, 9, thr)
+        torch.cuda.synchronize()
+        return ([_rows(ctx.search_trace(i)) for i in ids],
+                [from_csr(ctx.solution_download(i, bl.SLOT_BEST)) for i in ids])
+
+    lane, seg = run(0), run(bl.SEGMENT_EVAL)
+    assert lane == seg
+    assert any(r[4] for tr in lane[0] for r in tr), "no member improved"
+
+
 def test_search_graph_replays_match_eager(ctx):
     """A captured 3-iteration graph replayed 3 times, with eager work and
     synchronisation between replays, equals 9 eager iterations."""
