@@ -592,15 +592,24 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
 // The batched evaluation with one candidate per lane, for batches whose
 // members all have at most N tours and 32-bit time bounds: a member's tours
 // beyond its own count are empty and inactive (eval_lane's nt), so one
-// instantiation serves members of any smaller tour count.
+// instantiation serves members of any smaller tour count.  A candidate whose
+// SU rounds run past su_defer_rounds(N_T) is queued in LDS (up to
+// kLocalDefer per item) and evaluated again, densely, once the item's other
+// candidates are done.
+constexpr uint32_t kLocalDefer = 1024;
+
 template <int N, bool SMALL>
 __global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_item, s_qn;
+  __shared__ uint32_t s_q[kLocalDefer];
   __shared__ LaneBase s_base;
   int cur = -1;
   while (true) {
-    if (threadIdx.x == 0) s_item = atomicAdd(B.queue, 1u);
+    if (threadIdx.x == 0) {
+      s_item = atomicAdd(B.queue, 1u);
+      s_qn = 0;
+    }
     __syncthreads();
     const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads below
     if (item >= B.total_items) break;
@@ -626,10 +635,30 @@ __global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
     const int64_t t_star = P.st->t_best;
     const uint32_t idx = B.index_base + k;
     const int nt = P.NT;
+    const int su_limit = su_defer_rounds(nt);
     uint64_t best = kInfKey;
     for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
       const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
       if (!m.valid) continue;
+      LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, su_limit, nt);
+      if (o.deferred) {
+        const uint32_t slot = atomicAdd(&s_qn, 1u);
+        if (slot < kLocalDefer) {
+          s_q[slot] = c;
+          continue;
+        }
+        o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);   // no room: finish here
+      }
+      if (o.feasible && !is_gated(o.makespan, t_star, P.flags)) {
+        const uint64_t key = (o.cost << 24) | (uint64_t)c;
+        best = key < best ? key : best;
+      }
+    }
+    __syncthreads();
+    const uint32_t qn = s_qn < kLocalDefer ? s_qn : kLocalDefer;
+    for (uint32_t i = threadIdx.x; i < qn; i += blockDim.x) {
+      const uint32_t c = s_q[i];
+      const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
       const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);
       if (o.feasible && !is_gated(o.makespan, t_star, P.flags)) {
         const uint64_t key = (o.cost << 24) | (uint64_t)c;
