@@ -59,9 +59,10 @@ def kernel_source_digest():
 
 
 def recorded_traffic(workload):
-    """HBM bytes per evaluation launch from the committed counter summary of
-    this workload (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
-    readings), or None when there is none or the kernel has changed since."""
+    """HBM bytes per evaluation step (a lane kernel's two passes) from the
+    committed counter summary of this workload (FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy's readings), or None when there is none or the
+    kernel has changed since."""
     path = os.path.join(ROOT, "profiles", "k_eval_search_%s.md" % workload)
     if not os.path.exists(path):
         return None
@@ -74,7 +75,7 @@ def recorded_traffic(workload):
     if vals.get("kernel_source_sha256") != kernel_source_digest():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals["traffic_bytes_per_step"])
     except (KeyError, ValueError):
         return None
 
@@ -531,6 +532,8 @@ def main():
                      "kernel": ("k_eval_lane" if inst.n_tours <= LANE_MAX_TOURS else "k_eval") + " (search mode)",
                      "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
                      "kernel_ms_per_launch": per_launch_s * 1e3,
+                     # the lane kernel's evaluation step: first pass + pass over the deferred candidates
+                     "dispatches_per_launch": 2 if inst.n_tours <= LANE_MAX_TOURS else 1,
                      "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                              "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc,
                              "peak_measured": lds_meas, "frac_measured": achieved / lds_meas},
