@@ -427,7 +427,8 @@ def main():
     ap.add_argument("--workload", default="mid100", choices=sorted(DESCR) + ["batch256", "replica"])
     ap.add_argument("--replica-seeds", type=int, default=10)
     ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 14)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
+                    help="candidates the oracle evaluates for cpu_baseline (2^19: about 12 s on 16 host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-screen", action="store_true",
                     help="skip the plain vs screened wall-time comparison")
