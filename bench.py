@@ -533,8 +533,6 @@ def main():
                      "kernel": ("k_eval_lane" if inst.n_tours <= LANE_MAX_TOURS else "k_eval") + " (search mode)",
                      "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
                      "kernel_ms_per_launch": per_launch_s * 1e3,
-                     # the lane kernel's evaluation step: first pass + pass over the deferred candidates
-                     "dispatches_per_launch": 2 if inst.n_tours <= LANE_MAX_TOURS else 1,
                      "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                              "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc,
                              "peak_measured": lds_meas, "frac_measured": achieved / lds_meas},

@@ -239,6 +239,27 @@ def test_deferred_list_overflow(ctx, name):
     assert np.allclose(gc, oc[0], rtol=1e-5)
 
 
+@pytest.mark.parametrize("name", ["mid100", "clust500"])
+def test_two_pass_equals_segment(ctx, name):
+    """At 2^20 candidates the lane evaluation runs its two passes (long SU
+    tails deferred to the second); its outputs equal the segment version's
+    (one pass, one tour per lane) element for element."""
+    _say("two passes vs segment", name)
+    inst = _instance(name)
+    base = _walk_base(inst, OI.init_solution(inst), 5, 40)
+    a = _setup(ctx, inst, base)
+    g = _setup(ctx, inst, base, bl.SEGMENT_EVAL)
+    n = 1 << 20
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(a, 91, 2, 0, 0, n, d_mv)
+    words = d_mv.cpu().numpy().view(np.uint64)
+    ga = _gpu_eval(ctx, a, words, 1 << 40)
+    gg = _gpu_eval(ctx, g, words, 1 << 40)
+    for x, y in zip(ga, gg):
+        assert np.array_equal(x, y)
+    assert (ga[0] != bl.INF_KEY).any()
+
+
 def test_evaluate_invalid_and_ragged(ctx):
     _say("evaluate invalid")
     inst = _instance("tiny12")
