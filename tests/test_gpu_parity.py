@@ -239,16 +239,19 @@ def test_deferred_list_overflow(ctx, name):
     assert np.allclose(gc, oc[0], rtol=1e-5)
 
 
-@pytest.mark.parametrize("name", ["mid100", "clust500"])
-def test_two_pass_equals_segment(ctx, name):
+@pytest.mark.parametrize("name,caps", [("mid100", (0, 0)), ("clust500", (0, 0)),
+                                       ("mid100", (0, 4)), ("clust500", (2, 3))])
+def test_two_pass_equals_segment(ctx, name, caps):
     """At 2^20 candidates the lane evaluation runs its two passes (long SU
     tails deferred to the second); its outputs equal the segment version's
-    (one pass, one tour per lane) element for element."""
-    _say("two passes vs segment", name)
+    (one pass, one tour per lane) element for element, also where the SU cap
+    (4 at 5 tours, 3 at 10) lies just past the deferral limit (3 and 1
+    rounds), so that deferred candidates hit it in the second pass."""
+    _say("two passes vs segment", name, caps)
     inst = _instance(name)
     base = _walk_base(inst, OI.init_solution(inst), 5, 40)
-    a = _setup(ctx, inst, base)
-    g = _setup(ctx, inst, base, bl.SEGMENT_EVAL)
+    a = _setup(ctx, inst, base, 0, *caps)
+    g = _setup(ctx, inst, base, bl.SEGMENT_EVAL, *caps)
     n = 1 << 20
     d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
     ctx.generate(a, 91, 2, 0, 0, n, d_mv)
@@ -258,6 +261,8 @@ def test_two_pass_equals_segment(ctx, name):
     for x, y in zip(ga, gg):
         assert np.array_equal(x, y)
     assert (ga[0] != bl.INF_KEY).any()
+    if caps[1]:
+        assert (ga[3] & bl.CAND_CAP_SU).any()
 
 
 def test_evaluate_invalid_and_ragged(ctx):
