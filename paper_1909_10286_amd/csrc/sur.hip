@@ -1404,7 +1404,7 @@ __global__ void k_scr_export(const uint32_t *keys, uint32_t n, float *out) {
   }
 }
 
-// The judge of the screen.  Scatter: the standard deviation of (predicted -
+// How well the screen ranks.  Scatter: the standard deviation of (predicted -
 // exact) path over the shortlisted candidates with an exact cost, divided by
 // their mean exact cost (a common offset does not change the ranking, so it
 // is not counted).  Fallback when no shortlisted candidate passed the exact

@@ -177,7 +177,7 @@ def test_rebalance_first_sufficient_unit_and_inactive_donor():
 
 def test_rebalance_two_tours_fallback_donor():
     """With two tours there is no third tour to draw from: the donor is the
-    runner-up itself (reading of Alg. 2 line 3 at N_T = 2)."""
+    runner-up itself (reading of Alg. 2's donor choice at N_T = 2)."""
     s = {0: 10, 1: 10, 2: 10}
     units, rounds, _ = M.rebalance(2, [True, True], [{0}, {1, 2}],
                                    _linear_value([100, 60], s), lambda u: (s[u], u), 10)
