@@ -16,7 +16,7 @@ Readings of passages the paper leaves open (each one is listed in the design doc):
     shuttle driving per field (sec. 2.2);
   * completion time of a tour = road time of its route at the HU road speed
     plus its harvested area over the summed working rates of its HUs;
-  * waiting time (eq. (5) and Alg. 2 step 1): round trip of the mean
+  * waiting time (eq. (5) and Alg. 2's mean BP distance): round trip of the mean
     field-to-BP distance of the tour at the critical SU's speed, minus the
     fill times of the other SUs of the tour divided by the tour's HU count;
     the critical SU has the largest fill time;
@@ -144,7 +144,7 @@ def mean_bp_distance(inst, sol: Solution, b: int) -> int:
 
 
 def tour_mean_distance(inst, sol: Solution, g: int) -> int:
-    """Outer mean of Alg. 2 step 1 over the BPs of tour g that hold fields."""
+    """Outer mean of Alg. 2's mean BP distance over the BPs of tour g that hold fields."""
     bs = [b for b in sol.tours[g] if sol.fields[b]]
     if not bs:
         return 0
@@ -178,7 +178,7 @@ def critical_su(inst, sus) -> int:
 
 
 def waiting_time(inst, mean_dist_m: int, sus, n_hu: int) -> float:
-    """HU waiting time of a tour (eq. (5) averaged as in Alg. 2 step 1), in
+    """HU waiting time of a tour (eq. (5) with the distance averaged as in Alg. 2), in
     seconds: round trip of the mean field-BP distance at the critical SU's
     speed, minus the summed fill times of the other SUs over the HU count."""
     if not sus or n_hu == 0:
