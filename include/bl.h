@@ -6,7 +6,7 @@
  *
  * The library evaluates many candidate solutions x_i of the multi-tour
  * harvest problem at once (Algorithm 1, GPU version, sec. 2.5): each
- * candidate is one remove-and-reinsert move (Step 8) applied to a base
+ * candidate is one remove-and-reinsert move (Alg. 1) applied to a base
  * solution; its evaluation checks the demand constraints (eq. (2)), runs the
  * embedded min-max assignment of HUs and of SUs (sec. 2.5 and Algorithm 2)
  * and costs the total path length (sec. 2.2) with the makespan gate of
@@ -113,7 +113,7 @@ typedef struct {
 } bl_instance;
 
 /*
- * Solution x (sec. 2.5, Step 4): compressed lists.  Tour g visits BPs
+ * Solution x (sec. 2.5, Alg. 1): compressed lists.  Tour g visits BPs
  * tour_bp[tour_off[g] .. tour_off[g+1]) in order; BP b's fields, in harvest
  * order, are bp_field[bp_off[b] .. bp_off[b+1]) (BPs in id order).  hu_tour
  * and su_tour give each unit's tour.  The caller allocates every array.
@@ -165,7 +165,7 @@ const char *bl_last_error(const bl_ctx *ctx);
  * Writes its id to *inst.  Synchronising. */
 bl_status bl_instance_upload(bl_ctx *ctx, const bl_instance *in, int32_t *inst);
 
-/* Steps 1-3 of Algorithm 1 on the host: BPs to tours by one nearest-neighbour
+/* The initial solution of Algorithm 1 on the host: BPs to tours by one nearest-neighbour
  * chain from HQ (floor(n_bps / n_tours) per tour, residual to the last),
  * fields in id order to the closest BP with unmet demand (then the closest
  * BP), each BP's fields chained from HQ, units in contiguous id blocks.
@@ -179,7 +179,7 @@ bl_status bl_init_solution(bl_ctx *ctx, int32_t inst, bl_solution *out);
 bl_status bl_solution_upload(bl_ctx *ctx, int32_t inst, int32_t slot, const bl_solution *sol);
 bl_status bl_solution_download(bl_ctx *ctx, int32_t inst, int32_t slot, bl_solution *sol);
 
-/* Step 8 moves for candidates first .. first+n-1 of iteration `iter` drawn
+/* Remove-and-reinsert moves for candidates first .. first+n-1 of iteration `iter` drawn
  * against the base slot: Philox4x32-10 block with counter (i, iter,
  * inst_index, 0) under key `seed`; vertex uniform over fields and BPs,
  * destination BP or tour uniform, slot uniform over the destination list
@@ -201,7 +201,7 @@ bl_status bl_evaluate_batch(bl_ctx *ctx, int32_t inst, const uint64_t *d_moves, 
  * because keys carry the index.  Async. */
 bl_status bl_select_best(bl_ctx *ctx, const uint64_t *d_key, uint32_t n, uint64_t *d_best);
 
-/* Step 4: evaluate the base slot with the gate off, store its minimised units
+/* Start of Algorithm 1: evaluate the base slot with the gate off, store its minimised units
  * as x* and x_old, set C*, T*, and reset the trace (capacity trace_capacity
  * rows; further rows are counted but not stored).  Async. */
 bl_status bl_search_start(bl_ctx *ctx, int32_t inst, uint32_t trace_capacity);
@@ -237,7 +237,7 @@ typedef struct {
 
 bl_status bl_batch_create(bl_ctx *ctx, const int32_t *inst_ids, int32_t n_inst, uint32_t n_cand,
                           int32_t *batch);
-/* Step 4 for every member (as bl_search_start).  Async. */
+/* The start of Algorithm 1 for every member (as bl_search_start).  Async. */
 bl_status bl_batch_start(bl_ctx *ctx, int32_t batch, uint32_t trace_capacity);
 /* One iteration of Algorithm 1 for every member; p->n is ignored.  Async. */
 bl_status bl_batch_step(bl_ctx *ctx, int32_t batch, const bl_search_params *p);

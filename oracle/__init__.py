@@ -15,8 +15,8 @@ Modules:
   model    - supplies, shuttle drives, tour geometry, times, cost (sec. 2.1-2.3,
              eqs. (1)-(5)); the HU and SU min-max rebalancing (sec. 2.5, Alg. 2);
              feasibility (eq. (2)); candidate key and gate (sec. 2.5).
-  init     - initial solution, Steps 1-4 of Algorithm 1 (sec. 2.5).
-  moves    - Step 8 remove-and-reinsert moves drawn from Philox (sec. 2.5).
+  init     - initial solution of Algorithm 1 and its feasibility (sec. 2.5).
+  moves    - Alg. 1's remove-and-reinsert moves drawn from Philox (sec. 2.5).
   search   - Algorithm 1, GPU version, with the eq. (6) exploration rule.
   surrogate- float64 set-encoder network used to check the learned screen.
 

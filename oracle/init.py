@@ -1,10 +1,11 @@
-"""Initial solution: Steps 1-3 of Algorithm 1 (sec. 2.5).
+"""Initial solution of Algorithm 1 (sec. 2.5): BPs to tours, fields to BPs,
+field order.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Readings (listed in the design doc): Step 1 gives each tour floor(N_B / N_T) BPs of
+Readings of the paper: the BP-to-tour split gives each tour floor(N_B / N_T) BPs of
 one nearest-neighbour chain from HQ, the last tour the residual (the symbol in
-the paper's sentence is garbled); Step 2 takes fields in id order (the
+the paper's sentence is garbled); fields go to BPs in id order (the
 deterministic rule the paper names); nearest means smallest road distance,
 ties to the lowest id; every BP's field chain starts at HQ; units start in
 contiguous id blocks of floor(N / N_T), residual to the last tour, unless the
@@ -22,7 +23,7 @@ def _nearest(inst, cur: int, pool, vertex_of):
 
 
 def bp_chain(inst):
-    """Step 1 (ii): sequential nearest-neighbour search over BPs from HQ."""
+    """BPs to tours: sequential nearest-neighbour search over BPs from HQ."""
     chain, left, cur = [], list(range(inst.n_bps)), HQ
     while left:
         b = _nearest(inst, cur, left, bp_vertex)
@@ -45,7 +46,7 @@ def split_blocks(n: int, n_tours: int, counts=None):
 
 
 def assign_fields(inst):
-    """Step 2: fields in id order to the closest BP whose demand is not yet
+    """Fields to BPs: in id order to the closest BP whose demand is not yet
     met; once every demand is met, to the closest BP.  Returns the per-BP
     field lists (id order) or None if some demand stays unmet."""
     supplied = [0] * inst.n_bps
@@ -62,7 +63,7 @@ def assign_fields(inst):
 
 
 def order_fields(inst, fs):
-    """Step 3: nearest-neighbour chain over one BP's fields, from HQ."""
+    """Field order: nearest-neighbour chain over one BP's fields, from HQ."""
     out, left, cur = [], list(fs), HQ
     while left:
         f = _nearest(inst, cur, left, field_vertex)
@@ -87,6 +88,6 @@ def init_solution(inst) -> Optional[Solution]:
 
 
 def init_feasible(inst) -> bool:
-    """Acceptance predicate for the instance generator (greedy Step 2 meets
+    """Acceptance predicate for the instance generator (the greedy field-to-BP assignment meets
     every demand)."""
     return assign_fields(inst) is not None

@@ -7,7 +7,7 @@ kg, areas in 0.01 ha, working rates in 0.01 ha/h, speeds in m/h, times in
 seconds.  "Infinite" times are ``math.inf``.  Every division is a floor
 division of non-negative integers.
 
-Readings of passages the paper leaves open (each one is listed in the design doc):
+Readings of passages the paper leaves open:
   * supply s_f = area_f * yield_f (eq. (3) with a per-field yield);
   * shuttle drives n_f = ceil(s_f / c_bar) with c_bar the fleet-mean SU
     capacity, floor division (eq. (4) gives one count per SU class);
@@ -44,14 +44,14 @@ FLAG_INF_MAKESPAN = 32
 
 GATE_LE = "le"          # discard when T_max > T*  (default reading)
 GATE_STRICT = "strict"  # discard when T_max >= T* (literal reading)
-GATE_OFF = "off"        # no makespan gate (Case 2, and Step 4 of Alg. 1)
+GATE_OFF = "off"        # no makespan gate (Case 2, and Alg. 1's start)
 
 HQ = 0
 
 
 @dataclasses.dataclass
 class Solution:
-    """The generic solution vector x (sec. 2.5, Step 4 of Alg. 1).
+    """The generic solution vector x (sec. 2.5, Alg. 1).
 
     tours[g]  : BP ids visited by tour g, in order          (levels i, ii)
     fields[b] : field ids assigned to BP b, in harvest order (levels iii, iv)
@@ -137,8 +137,8 @@ def tour_area(inst, sol: Solution, g: int) -> int:
 
 
 def mean_bp_distance(inst, sol: Solution, b: int) -> int:
-    """Mean field-to-BP distance of the fields of BP b (inner mean of Alg. 2
-    step 1), floor division; the BP must hold at least one field."""
+    """Mean field-to-BP distance of the fields of BP b (inner mean of Alg. 2's
+    mean BP distance), floor division; the BP must hold at least one field."""
     fs = sol.fields[b]
     return sum(dist(inst, field_vertex(inst, f), bp_vertex(inst, b)) for f in fs) // len(fs)
 

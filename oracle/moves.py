@@ -1,9 +1,9 @@
-"""Step 8 of Algorithm 1: remove one vertex (field or BP) and reinsert it
+"""The move of Algorithm 1: remove one vertex (field or BP) and reinsert it
 (sec. 2.5), drawn from the counter-based generator.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Readings (listed in the design doc): the vertex is uniform over the N_F + N_B
+Readings of the paper: the vertex is uniform over the N_F + N_B
 vertices; a field goes to a uniform BP (its own included; with the fixed
 field-to-BP variant of sec. 2.6 it stays in its own BP), a BP to a uniform tour
 (its own included) and carries all of its fields; the slot is uniform over the

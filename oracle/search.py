@@ -4,7 +4,7 @@ its random draw, update of x* and x_old.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Readings (listed in the design doc): Step 4 evaluates the initial x with the gate
+Readings of the paper: the start evaluates the initial x with the gate
 off and keeps its minimised units; a candidate starts from the units of its
 base; x* is replaced only on a strict decrease of C (and then T* becomes the
 winner's makespan); when every candidate is discarded x_old becomes the base;
@@ -68,7 +68,7 @@ def with_units(sol: M.Solution, ev: M.Evaluation) -> M.Solution:
 
 
 def start(inst, x0: M.Solution, caps=None, embedded_min: bool = True) -> SearchState:
-    """Step 4: summarise the initial solution as x*, cost it, x_old = x*."""
+    """Start of Alg. 1: summarise the initial solution as x*, cost it, x_old = x*."""
     ev = M.evaluate_solution(inst, x0, caps, embedded_min)
     assert ev.feasible
     xb = with_units(x0, ev)

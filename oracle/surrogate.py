@@ -24,7 +24,7 @@ definition; the GPU kernels are checked against it.
 
 Scales: Ls = largest |coordinate|, As / Ys = largest area / yield, Ds =
 largest distance, Ws = largest 2 n_f D(f,b); C0, T0 = path length and
-makespan of the initial solution after Step 4.  The units are the
+makespan of the initial solution after Alg. 1's start.  The units are the
 candidate's units before rebalancing (those of its base).
 """
 from __future__ import annotations

@@ -1,5 +1,5 @@
 // Device helpers shared by the evaluator and the learned-screen kernels:
-// Philox, the LDS view of an instance image, Step 8 move decoding and the
+// Philox, the LDS view of an instance image, remove-and-reinsert move decoding and the
 // candidate view, segment reductions, unit masks, the full evaluation of one
 // candidate (walk, eq. (2), HU and SU rebalancing, cost) and LDS staging.
 #pragma once
@@ -154,7 +154,7 @@ __device__ __forceinline__ Move decode_move(uint64_t w, const View &V, const Ins
   return m;
 }
 
-// Step 8 draw of candidate i of iteration `it` (counter (i, it, inst, 0)).
+// Remove-and-reinsert draw of candidate i of iteration `it` (counter (i, it, inst, 0)).
 __device__ __forceinline__ uint64_t draw_move(uint64_t seed, uint32_t i, uint32_t it,
                                               uint32_t inst_index, const View &V,
                                               const InstParams &P) {

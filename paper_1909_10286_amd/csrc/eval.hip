@@ -1,4 +1,4 @@
-// gfx950 kernels of the candidate evaluator: base preparation, Step 8 move
+// gfx950 kernels of the candidate evaluator: base preparation, move
 // generation, candidate evaluation (walk, eq. (2) check, HU and SU min-max
 // rebalancing, path-length cost, makespan gate), argmin, and the commit of
 // the winner (Algorithm 1, GPU version, sec. 2.5 of the paper).
@@ -416,7 +416,7 @@ __global__ void k_select(const uint64_t *__restrict__ keys, uint32_t n, uint64_t
     atomicMin((unsigned long long *)out, (unsigned long long)best);
 }
 
-// Commit (one workgroup).  Start mode: Step 4 of Algorithm 1, the base with
+// Commit (one workgroup).  Start mode: the start of Algorithm 1, the base with
 // a no-op move and the gate off becomes x* and x_old.  Step mode: the winner
 // of the iteration is rebuilt from its draw, x_old <- x_new, and x* <- x_new
 // on a strict decrease of C; one trace row.

@@ -1,5 +1,5 @@
 // Host side of the C interface: contexts, instance validation and upload,
-// the initial solution (Steps 1-3 of Algorithm 1), solution slots, and the
+// the initial solution of Algorithm 1, solution slots, and the
 // launch sequence of the device-resident search iteration.
 #include <hip/hip_runtime.h>
 
@@ -700,7 +700,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   return BL_OK;
 }
 
-// Steps 1-3 of Algorithm 1 (sec. 2.5), on the host.
+// The initial solution of Algorithm 1 (sec. 2.5), on the host.
 bl_status bl_init_solution(bl_ctx *c, int32_t id, bl_solution *out) {
   Instance *I = get_inst(c, id);
   if (!I) return fail(c, BL_EINVAL, "bad instance id %d", id);
@@ -709,7 +709,7 @@ bl_status bl_init_solution(bl_ctx *c, int32_t id, bl_solution *out) {
     return fail(c, BL_EINVAL, "solution: null array");
   const int NF = I->NF, NB = I->NB, NT = I->NT, V = I->V;
   auto D = [&](int a, int b) { return I->dist[(size_t)a * V + b]; };
-  // Step 1: nearest-neighbour chain over the BPs from HQ, ties to the lower id.
+  // BPs to tours: nearest-neighbour chain over the BPs from HQ, ties to the lower id.
   std::vector<int> chain;
   std::vector<char> used(NB, 0);
   int cur = 0;
@@ -724,7 +724,7 @@ bl_status bl_init_solution(bl_ctx *c, int32_t id, bl_solution *out) {
   const int per = NB / NT;
   for (int g = 0; g <= NT; ++g) out->tour_off[g] = (uint16_t)(g < NT ? g * per : NB);
   for (int j = 0; j < NB; ++j) out->tour_bp[j] = (uint16_t)chain[j];
-  // Step 2: fields in id order to the closest BP with unmet demand, then to
+  // Fields to BPs: in id order to the closest BP with unmet demand, then to
   // the closest BP.
   std::vector<uint64_t> got(NB, 0);
   std::vector<std::vector<int>> lists(NB);
@@ -741,7 +741,7 @@ bl_status bl_init_solution(bl_ctx *c, int32_t id, bl_solution *out) {
   }
   for (int b = 0; b < NB; ++b)
     if (got[b] < I->demand[b]) return fail(c, BL_EINFEASIBLE, "BP %d demand unmet by the greedy assignment", b);
-  // Step 3: per BP, nearest-neighbour chain over its fields from HQ.
+  // Field order: per BP, nearest-neighbour chain over its fields from HQ.
   int o = 0;
   for (int b = 0; b < NB; ++b) {
     out->bp_off[b] = (uint16_t)o;

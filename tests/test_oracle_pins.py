@@ -253,7 +253,7 @@ def test_su_loop_vs_exhaustive_split():
 # ------------------------------------------------------------------- init --
 
 def test_init_hand_instance():
-    """Steps 1-3 on a hand instance: BPs on the x axis at 1000, 3000, -2000;
+    """The initial solution of Alg. 1 on a hand instance: BPs on the x axis at 1000, 3000, -2000;
     the NN chain from HQ is B0, B1, B2; floor(3/2) = 1 BP for tour 0, the rest
     for tour 1; fields go to the nearest BP with unmet demand; each BP's
     fields are chained from HQ."""
