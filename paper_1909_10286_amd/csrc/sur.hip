@@ -380,27 +380,55 @@ __global__ __launch_bounds__(256) void k_sur_bwd(SurDev S, uint32_t n_rows) {
   for (int k = 0; k < 2; ++k) acc1[k] = floatx4{0.f, 0.f, 0.f, 0.f};
   float gb2[4] = {0.f, 0.f, 0.f, 0.f}, gb1[4] = {0.f, 0.f, 0.f, 0.f};
   const uint32_t chunks = (n_rows + 31) / 32;
+  // A chunk's rows are loaded into registers one chunk ahead, so that the
+  // loads of chunk ch + gridDim.x are in flight while chunk ch is on MFMA.
+  // Thread t holds elements t + 256 k of the chunk's dP (32 x 64), h1 and h2
+  // (32 x 128) and phi (32 x 16) tiles; rows past n_rows are zero.
+  static_assert(32 * 64 % 256 == 0 && 32 * 128 % 256 == 0 && 32 * 16 % 256 == 0, "tile split");
+  float pf_dp[32 * 64 / 256];
+  uint16_t pf_h1[32 * 128 / 256], pf_h2[32 * 128 / 256], pf_phi[32 * 16 / 256];
+  auto fetch = [&](uint32_t row0) {
+#pragma unroll
+    for (int k = 0; k < 32 * 64 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 6, cc = i & 63;
+      pf_dp[k] = row0 + rr < n_rows ? S.dP[(size_t)(row0 + rr) * kSurA + cc] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 32 * 128 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 7, cc = i & 127;
+      const bool v = row0 + rr < n_rows;
+      pf_h1[k] = v ? S.h1[(size_t)(row0 + rr) * 128 + cc] : (uint16_t)0;
+      pf_h2[k] = v ? S.h2[(size_t)(row0 + rr) * 128 + cc] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 32 * 16 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 4, cc = i & 15;
+      pf_phi[k] = row0 + rr < n_rows ? S.phi[(size_t)(row0 + rr) * kSurK1 + cc] : (uint16_t)0;
+    }
+  };
+  if (blockIdx.x < chunks) fetch(blockIdx.x * 32);
   for (uint32_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
-    const uint32_t row0 = ch * 32;
     __syncthreads();
-    for (int i = threadIdx.x; i < 32 * 64; i += blockDim.x) {
-      const int rr = i >> 6, cc = i & 63;
-      const float v = row0 + rr < n_rows ? S.dP[(size_t)(row0 + rr) * kSurA + cc] : 0.f;
-      const uint16_t bv = to_bf16(v);
+#pragma unroll
+    for (int k = 0; k < 32 * 64 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 6, cc = i & 63;
+      const uint16_t bv = to_bf16(pf_dp[k]);
       dPr[rr * kLd3 + cc] = bv;
       dPT[cc * kLd1 + rr] = bv;
     }
-    for (int i = threadIdx.x; i < 32 * 128; i += blockDim.x) {
-      const int rr = i >> 7, cc = i & 127;
-      const bool v = row0 + rr < n_rows;
-      h1T[cc * kLd1 + rr] = v ? S.h1[(size_t)(row0 + rr) * 128 + cc] : (uint16_t)0;
-      h2T[cc * kLd1 + rr] = v ? S.h2[(size_t)(row0 + rr) * 128 + cc] : (uint16_t)0;
+#pragma unroll
+    for (int k = 0; k < 32 * 128 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 7, cc = i & 127;
+      h1T[cc * kLd1 + rr] = pf_h1[k];
+      h2T[cc * kLd1 + rr] = pf_h2[k];
     }
-    for (int i = threadIdx.x; i < 32 * 16; i += blockDim.x) {
-      const int rr = i >> 4, cc = i & 15;
-      phiT[cc * kLd1 + rr] = row0 + rr < n_rows ? S.phi[(size_t)(row0 + rr) * kSurK1 + cc] : (uint16_t)0;
+#pragma unroll
+    for (int k = 0; k < 32 * 16 / 256; ++k) {
+      const int i = threadIdx.x + 256 * k, rr = i >> 4, cc = i & 15;
+      phiT[cc * kLd1 + rr] = pf_phi[k];
     }
     __syncthreads();
+    if (ch + gridDim.x < chunks) fetch((ch + gridDim.x) * 32);
     // dz2 = (dP W3e^T) * (h2 > 0): 16 tiles (2 row tiles x 8 column tiles), 4 per wave.
     for (int k = 0; k < 4; ++k) {
       const int tile = wave * 4 + k, rt = tile >> 3, nt = tile & 7;
