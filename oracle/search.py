@@ -1,6 +1,8 @@
-"""Algorithm 1, GPU version (sec. 2.5): n candidates per iteration, argmin of
-the path length over the non-discarded ones, reconstruction of the winner from
-its random draw, update of x* and x_old.
+"""Algorithm 1 (sec. 2.5).  GPU version: n candidates per iteration, argmin
+of the path length over the non-discarded ones, reconstruction of the winner
+from its random draw, update of x* and x_old.  CPU version: one candidate per
+iteration, x_old <- x after every draw (``search_cpu_version``); the GPU
+version with one worker is ``search_single_worker``.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -129,16 +131,15 @@ def search(inst, x0: M.Solution, seed: int, n: int, iters: int, eps_threshold: i
     return st
 
 
-def search_cpu_version(inst, x0: M.Solution, seed: int, iters: int, eps_threshold: int,
-                       gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
-                       caps=None, embedded_min: bool = True) -> SearchState:
-    """Algorithm 1, CPU version: each iteration draws one remove-and-reinsert
-    move on the eq. (6) base, checks eq. (2), evaluates the candidate (units,
-    cost, makespan gate), keeps it as x* on a strict decrease of C, and
-    continues from it.  A candidate that fails eq. (2) or the gate is not
-    taken: the base is kept (the reading that makes this the GPU version
-    with a single worker).  It is written out here rather than delegated so
-    that the branch can be read against the algorithm."""
+def search_single_worker(inst, x0: M.Solution, seed: int, iters: int, eps_threshold: int,
+                         gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
+                         caps=None, embedded_min: bool = True) -> SearchState:
+    """Algorithm 1, GPU version with a single worker (n = 1), written out: each
+    iteration draws one remove-and-reinsert move on the eq. (6) base; a
+    candidate that fails eq. (2) or the makespan gate is discarded and x_old
+    becomes the base (as when every worker's candidate is discarded);
+    otherwise x_old becomes the candidate with its minimised units and x* is
+    replaced on a strict decrease of C."""
     st = start(inst, x0, caps, embedded_min)
     for _ in range(iters):
         it = st.it
@@ -157,6 +158,48 @@ def search_cpu_version(inst, x0: M.Solution, seed: int, iters: int, eps_threshol
                 indicator = 1 if mv.kind == FIELD else 2
         trace = st.trace + [TraceRow(it, use_best, r.key, cb, tb, indicator)]
         st = SearchState(it + 1, xb, cb, tb, x_old, trace)
+    return st
+
+
+def cpu_version_step(inst, st: SearchState, seed: int, eps_threshold: int, gate: str = M.GATE_LE,
+                     inst_idx: int = 0, fixed_field_bp: bool = False, caps=None,
+                     embedded_min: bool = True) -> SearchState:
+    """One iteration of Algorithm 1, CPU version, as the algorithm states it:
+    x is taken from x_old or x* by the eq. (6) rule; one random vertex of x is
+    removed and reinserted; eq. (2) is checked and, if x is feasible, x is
+    evaluated (the embedded HU and SU minimisation, path length, makespan
+    gate); x* is replaced when x is feasible, not discarded by the gate and
+    strictly cheaper; then x_old <- x whatever the checks gave.  x carries its
+    minimised units when it was evaluated, else the units of the solution it
+    came from; an x_old that breaks eq. (2) is kept, and later moves start
+    from it.  The draw of iteration it is Philox block (0, it, inst, 0), as
+    for candidate 0 of the GPU version."""
+    it = st.it
+    use_best = exploit_draw(seed, it, inst_idx, eps_threshold)
+    x = st.x_best if use_best else st.x_old
+    mv = draw_move(inst, x, seed, it, 0, inst_idx, fixed_field_bp)
+    r = evaluate_move(inst, x, mv, 0, gate, st.t_best, caps, embedded_min)
+    x = apply_move(x, mv) if is_valid(inst, x, mv) else x
+    if r.evaluation is not None and r.evaluation.feasible:
+        x = with_units(x, r.evaluation)
+    xb, cb, tb = st.x_best, st.cost_best, st.t_best
+    indicator = 0
+    if r.key != M.INF_KEY and r.evaluation.cost_m < st.cost_best:
+        xb, cb, tb = x, r.evaluation.cost_m, r.evaluation.makespan_s
+        indicator = 1 if mv.kind == FIELD else 2
+    trace = st.trace + [TraceRow(it, use_best, r.key, cb, tb, indicator)]
+    return SearchState(it + 1, xb, cb, tb, x, trace)
+
+
+def search_cpu_version(inst, x0: M.Solution, seed: int, iters: int, eps_threshold: int,
+                       gate: str = M.GATE_LE, inst_idx: int = 0, fixed_field_bp: bool = False,
+                       caps=None, embedded_min: bool = True) -> SearchState:
+    """Algorithm 1, CPU version: the start, then ``iters`` calls of
+    ``cpu_version_step``."""
+    st = start(inst, x0, caps, embedded_min)
+    for _ in range(iters):
+        st = cpu_version_step(inst, st, seed, eps_threshold, gate, inst_idx, fixed_field_bp, caps,
+                              embedded_min)
     return st
 
 

@@ -26,6 +26,10 @@ Scales: Ls = largest |coordinate|, As / Ys = largest area / yield, Ds =
 largest distance, Ws = largest 2 n_f D(f,b); C0, T0 = path length and
 makespan of the initial solution after Alg. 1's start.  The units are the
 candidate's units before rebalancing (those of its base).
+
+Training takes Adam steps (Kingma and Ba, "Adam: A Method for Stochastic
+Optimization", ICLR 2015, Algorithm 1) on the mean loss of a batch of
+examples: ``adam_step``.
 """
 from __future__ import annotations
 
@@ -195,3 +199,25 @@ def example_loss_and_grad(p, inst, sol, sc, cost_m, makespan_s):
     P, M, cache = forward(p, phi, u, fbp, btour, active, inst.n_bps)
     pt, mt = cost_m / sc.c0, makespan_s / sc.t0
     return loss(P, M, pt, mt), backward(p, cache, P, M, pt, mt)
+
+
+def adam_step(p, g, m, v, t, lr, beta1, beta2, eps):
+    """One Adam update (Kingma and Ba 2015, Algorithm 1) of every parameter
+    array in the dict p with gradient g, first and second moment estimates m
+    and v (dicts of the same shapes, zero before the first step) and step
+    number t >= 1.  Returns the new (p, m, v); nothing is changed in place.
+
+      m_t = beta1 m_{t-1} + (1 - beta1) g
+      v_t = beta2 v_{t-1} + (1 - beta2) g^2
+      p_t = p_{t-1} - lr (m_t / (1 - beta1^t)) / (sqrt(v_t / (1 - beta2^t)) + eps)
+    """
+    assert t >= 1
+    bc1 = 1.0 - beta1 ** t
+    bc2 = 1.0 - beta2 ** t
+    p_new, m_new, v_new = {}, {}, {}
+    for k in p:
+        gk = np.asarray(g[k], dtype=np.float64)
+        m_new[k] = beta1 * np.asarray(m[k], dtype=np.float64) + (1.0 - beta1) * gk
+        v_new[k] = beta2 * np.asarray(v[k], dtype=np.float64) + (1.0 - beta2) * gk * gk
+        p_new[k] = np.asarray(p[k], dtype=np.float64) - lr * (m_new[k] / bc1) / (np.sqrt(v_new[k] / bc2) + eps)
+    return p_new, m_new, v_new

@@ -358,15 +358,16 @@ def test_search_trajectory_reduced(ctx, pool, name, n, iters, eps, flags):
 
 
 @pytest.mark.parametrize("name,iters", [("tiny12", 300), ("mid100", 120)])
-def test_cpu_version_is_the_single_worker_search(ctx, name, iters):
-    """Algorithm 1's CPU version (one candidate per iteration, the oracle's
-    `search_cpu_version`) equals the device-resident iteration with n = 1."""
-    _say("cpu version", name, iters)
+def test_single_worker_search(ctx, name, iters):
+    """The GPU version of Algorithm 1 with one worker (the oracle's
+    `search_single_worker`, one candidate per iteration) equals the
+    device-resident iteration with n = 1."""
+    _say("single worker", name, iters)
     inst = _instance(name)
     x0 = OI.init_solution(inst)
     thr = S.eps_threshold(0.5)
     iid, gtr, gst = _gpu_search(ctx, inst, x0, 4, 1, iters, thr)
-    st = S.search_cpu_version(inst, x0, 4, iters, thr)
+    st = S.search_single_worker(inst, x0, 4, iters, thr)
     _compare_trace(gtr, st.trace)
     assert from_csr(ctx.solution_download(iid, bl.SLOT_BEST)) == st.x_best
     assert from_csr(ctx.solution_download(iid, bl.SLOT_OLD)) == st.x_old

@@ -250,6 +250,108 @@ def test_su_loop_vs_exhaustive_split():
     assert got - best == 1365
 
 
+def _ties():
+    g = load_golden("three_tour_ties.json")
+    inst = build(g["xy_m"], g["n_bps"], g["n_tours"], g["field_area"], g["field_yield"],
+                 g["bp_demand_kg"], g["hu_rate"], g["su_cap_kg"], g["su_speed_mph"],
+                 g["su_fill_s"], road_factor=g["road_factor"])
+    s = g["solution"]
+    return inst, M.Solution(s["tours"], s["fields"], s["hu_tour"], s["su_tour"]), g["expected"]
+
+
+def test_three_tour_mean_distance_and_waiting_time():
+    """Alg. 2's mean BP distance is the mean over the tour's BPs (those with
+    fields) of each BP's mean, and eq. (5) divides the other SUs' fill times
+    by the tour's HU count; the critical SU of a fill-time tie is the lower
+    id.  Hand values (tests/golden/three_tour_ties.json) with the initial
+    units, no round taken: a flat mean over the fields, counting the empty
+    BP, skipping the division, or the other tied SU each change them."""
+    inst, sol, want = _ties()
+    assert [M.tour_length(inst, sol, g) for g in range(3)] == want["length_m"]
+    assert [M.tour_mean_distance(inst, sol, g) for g in range(3)] == want["mean_dist_m"]
+    ev = M.evaluate_solution(inst, sol, caps=(0, 0))
+    assert ev.feasible and ev.flags == M.FLAG_CAP_HU | M.FLAG_CAP_SU
+    assert ev.t_compl == want["initial"]["t_compl_s"]
+    assert ev.t_wait == want["initial"]["t_wait_s"]
+    assert ev.cost_m == want["initial"]["cost_m"]
+    assert ev.hu_tour == sol.hu_tour and ev.su_tour == sol.su_tour
+
+
+def test_three_tour_rebalancing_rounds_with_ties():
+    """sec. 2.5 HU step then Alg. 2: HUs tied in rate are tried in id order,
+    SUs tied in fill time in falling id order; each loop keeps one round and
+    undoes the second.  Every figure is the fixture's hand derivation."""
+    inst, sol, want = _ties()
+    fin = want["final"]
+    ev = M.evaluate_solution(inst, sol)
+    assert ev.feasible and ev.flags == 0
+    assert ev.hu_tour == fin["hu_tour"] and ev.su_tour == fin["su_tour"]
+    assert (ev.hu_rounds, ev.su_rounds) == (fin["hu_rounds"], fin["su_rounds"])
+    assert ev.t_compl == fin["t_compl_s"] and ev.t_wait == fin["t_wait_s"]
+    assert ev.makespan_s == fin["makespan_s"]
+    assert ev.cost_m == fin["cost_m"] and ev.tour_cost_m == fin["tour_cost_m"]
+    # One round each: the same units (the second rounds are undone), and the
+    # cap is reached because a second round was wanted.
+    one = M.evaluate_solution(inst, sol, caps=(1, 1))
+    assert one.hu_tour == fin["hu_tour"] and one.su_tour == fin["su_tour"]
+    assert one.flags == M.FLAG_CAP_HU | M.FLAG_CAP_SU and one.cost_m == fin["cost_m"]
+
+
+def test_all_discarded_sets_x_old_to_the_base():
+    """Reading of Alg. 1, GPU version, when every worker's candidate is
+    discarded: x_old becomes the base.  With T* forced below every makespan
+    each candidate is gated; the base is x* (eps = 1) while x_old was another
+    solution, so x_old must turn into x*, and nothing else changes."""
+    inst = inputs.make_instance("tiny12", 0, accept=OI.init_feasible)
+    x0 = OI.init_solution(inst)
+    st = S.start(inst, x0)
+    mv = next(m for m in (MV.draw_move(inst, st.x_best, 3, 0, i) for i in range(64))
+              if M.is_feasible(inst, MV.apply_move(st.x_best, m))
+              and MV.apply_move(st.x_best, m).fields != st.x_best.fields)
+    other = MV.apply_move(st.x_best, mv)
+    st = S.SearchState(st.it, st.x_best, st.cost_best, 0, other, [])
+    nxt = S.step(inst, st, seed=1, n=128, eps_threshold=1 << 32)
+    row = nxt.trace[-1]
+    assert row.best_key == M.INF_KEY and row.indicator == 0 and row.use_best
+    assert nxt.x_old == st.x_best and nxt.x_old != other
+    assert nxt.x_best == st.x_best and nxt.cost_best == st.cost_best and nxt.t_best == 0
+    # With the base x_old (eps = 0) the discarded iteration leaves x_old as it was.
+    nxt = S.step(inst, st, seed=1, n=128, eps_threshold=0)
+    assert nxt.trace[-1].best_key == M.INF_KEY and nxt.x_old == other
+
+
+def _three_bp_line_instance():
+    """One tour, three BPs of one field each; the initial BP order sends the
+    route across HQ twice, so reordering BPs shortens it."""
+    xy = [[0, 0], [11000, 0], [-11000, 0], [11000, 1000],
+          [10000, 0], [-10000, 0], [10000, 1000]]
+    return build(xy, 3, 1, [1000] * 3, [400] * 3, [100_000] * 3, [250], [20000, 30000],
+                 [40000, 45000], [576, 864])
+
+
+def test_indicator_two_for_an_improving_bp_move():
+    """Fig. 3 caption: the indicator is 2 when x* improved through a BP move.
+    Each BP holds one field and fields keep their BP (sec. 2.6 variant), so
+    every field move puts its field back where it was and only BP moves can
+    shorten the route HQ -> f0 -> f1 -> f2 -> HQ (60075 m) to 41025 m."""
+    inst = _three_bp_line_instance()
+    x0 = M.Solution([[0, 1, 2]], [[0], [1], [2]], [0], [0, 0])
+    st = S.start(inst, x0)
+    assert M.tour_length(inst, x0, 0) == 10000 + 20000 + 20025 + 10050
+    nxt = S.step(inst, st, seed=0, n=64, eps_threshold=1 << 32, fixed_field_bp=True)
+    row = nxt.trace[-1]
+    assert row.cost_m < st.cost_best and row.indicator == 2
+    win = MV.draw_move(inst, x0, 0, 0, row.best_key & 0xFFFFFF, fixed_field_bp=True)
+    assert win.kind == MV.BP
+    assert M.tour_length(inst, nxt.x_best, 0) == 41025
+    # One BP, one tour: only field moves exist, and every improvement is a 1.
+    inst1 = _single_tour_instance(0, 6)
+    full = S.search(inst1, OI.init_solution(inst1), seed=0, n=256, iters=40,
+                    eps_threshold=S.eps_threshold(0.5))
+    ind = [r.indicator for r in full.trace]
+    assert 1 in ind and set(ind) <= {0, 1}
+
+
 # ------------------------------------------------------------------- init --
 
 def test_init_hand_instance():
@@ -442,10 +544,12 @@ def test_instance_generator_invariants():
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_cpu_version_reaches_tsp_optimum_single_tour(seed):
-    """Algorithm 1's CPU version (one candidate per iteration) on the
-    one-tour instance: it never goes below the brute-force TSP optimum and
-    reaches it, its trace is monotone, and it is the GPU version with a
-    single worker."""
+    """Algorithm 1's CPU version (one candidate per iteration, x_old <- x) on
+    the one-tour instance: it never goes below the brute-force TSP optimum
+    and reaches it, and its trace is monotone.  With one BP and one tour every
+    move keeps eq. (2), so without the makespan gate the literal branch and the
+    GPU version with one worker take the same steps; with it they part at the
+    first discarded draw (the CPU version moves on from it)."""
     nf = 5
     inst = _single_tour_instance(seed, nf)
     x0 = OI.init_solution(inst)
@@ -459,7 +563,50 @@ def test_cpu_version_reaches_tsp_optimum_single_tour(seed):
     assert st.cost_best == 3 * best + shuttle
     costs = [r.cost_m for r in st.trace]
     assert all(a >= b for a, b in zip(costs, costs[1:]))
-    one = S.search(inst, x0, seed=seed, n=1, iters=600, eps_threshold=thr)
-    assert [(r.best_key, r.cost_m, r.use_best) for r in one.trace] == \
-        [(r.best_key, r.cost_m, r.use_best) for r in st.trace]
+    assert all(r.indicator in (0, 1) for r in st.trace)   # one BP: only field moves improve
+    one = S.search_single_worker(inst, x0, seed=seed, iters=600, eps_threshold=thr)
+    assert [r.best_key for r in one.trace] != [r.best_key for r in st.trace]
+    off = S.search_cpu_version(inst, x0, seed=seed, iters=200, eps_threshold=thr, gate=M.GATE_OFF)
+    one = S.search_single_worker(inst, x0, seed=seed, iters=200, eps_threshold=thr, gate=M.GATE_OFF)
+    assert one.trace == off.trace and one.x_old == off.x_old
+
+
+def test_single_worker_is_gpu_version_with_one_candidate():
+    """The GPU version with n = 1 written out equals the iteration loop with
+    n = 1, trace, x* and x_old."""
+    inst = inputs.make_instance("tiny12", 2, accept=OI.init_feasible)
+    x0 = OI.init_solution(inst)
+    thr = S.eps_threshold(0.5)
+    st = S.search_single_worker(inst, x0, seed=5, iters=300, eps_threshold=thr)
+    one = S.search(inst, x0, seed=5, n=1, iters=300, eps_threshold=thr)
+    assert one.trace == st.trace
     assert one.x_old == st.x_old and one.x_best == st.x_best
+
+
+def test_cpu_version_keeps_the_moved_x_whatever_the_checks():
+    """Algorithm 1, CPU version: x_old <- x after the remove-and-reinsert step
+    even when x breaks eq. (2); x* only ever holds feasible solutions whose
+    cost is C*.  On tiny12 (3 BPs at 80 % of the supply) a field leaving its
+    BP often breaks that BP's demand: after such a draw x_old is the
+    infeasible x with the units of the solution it came from, where the GPU
+    version's single worker would keep the base."""
+    inst = inputs.make_instance("tiny12", 0, accept=OI.init_feasible)
+    x0 = OI.init_solution(inst)
+    thr = S.eps_threshold(0.5)
+    st = S.start(inst, x0)
+    infeasible_kept = 0
+    for it in range(80):
+        x = st.x_best if MV.exploit_draw(0, it, 0, thr) else st.x_old
+        mv = MV.draw_move(inst, x, 0, it, 0)
+        moved = MV.apply_move(x, mv)
+        nxt = S.cpu_version_step(inst, st, 0, thr)
+        assert nxt.x_old.tours == moved.tours and nxt.x_old.fields == moved.fields
+        if not M.is_feasible(inst, moved):
+            infeasible_kept += 1
+            assert not M.is_feasible(inst, nxt.x_old)
+            assert nxt.x_old.hu_tour == x.hu_tour and nxt.x_old.su_tour == x.su_tour
+            assert nxt.trace[-1].best_key == M.INF_KEY and nxt.x_best is st.x_best
+        assert M.is_feasible(inst, nxt.x_best)
+        assert M.evaluate_solution(inst, nxt.x_best).cost_m == nxt.cost_best
+        st = nxt
+    assert infeasible_kept > 0

@@ -82,3 +82,60 @@ def test_inactive_tours_are_masked():
     assert list(active) == [False, True]
     P, Mk, cache = SG.forward(p, phi, u, fbp, btour, active, inst.n_bps)
     assert P == pytest.approx(cache["y"][1, 0]) and Mk == pytest.approx(cache["y"][1, 1])
+
+
+# ------------------------------------------------------------------- Adam --
+
+def _rand_params(rng):
+    return {"W": rng.normal(0, 1, (5, 3)), "b": rng.normal(0, 1, 3)}
+
+
+def test_adam_first_step_closed_form():
+    """Kingma and Ba (2015), Algorithm 1, at t = 1: the bias corrections undo
+    the (1 - beta) factors, so the step is -lr g / (|g| + eps) element-wise,
+    whatever beta1 and beta2 are."""
+    rng = np.random.default_rng(1)
+    p, g = _rand_params(rng), _rand_params(rng)
+    zero = {k: np.zeros_like(v) for k, v in p.items()}
+    for beta1, beta2 in ((0.9, 0.999), (0.5, 0.9)):
+        q, m, v = SG.adam_step(p, g, zero, zero, 1, 1e-3, beta1, beta2, 1e-8)
+        for k in p:
+            np.testing.assert_allclose(q[k] - p[k], -1e-3 * g[k] / (np.abs(g[k]) + 1e-8),
+                                       rtol=1e-12, atol=1e-18)
+            np.testing.assert_allclose(m[k], (1 - beta1) * g[k], rtol=1e-15)
+            np.testing.assert_allclose(v[k], (1 - beta2) * g[k] ** 2, rtol=1e-15)
+
+
+def test_adam_constant_gradient_steps():
+    """With the same gradient every step, m_t = (1 - beta1^t) g and v_t = (1 -
+    beta2^t) g^2 exactly (geometric sums), so every step is -lr g / (|g| +
+    eps): after k steps p moved by -k lr g / (|g| + eps)."""
+    rng = np.random.default_rng(2)
+    p, g = _rand_params(rng), _rand_params(rng)
+    m = v = {k: np.zeros_like(x) for k, x in p.items()}
+    q = p
+    for t in range(1, 8):
+        q, m, v = SG.adam_step(q, g, m, v, t, 2e-3, 0.9, 0.99, 1e-6)
+    for k in p:
+        np.testing.assert_allclose(q[k] - p[k], -7 * 2e-3 * g[k] / (np.abs(g[k]) + 1e-6), rtol=1e-9)
+
+
+def test_adam_matches_torch_optimizer():
+    """The library routine: torch.optim.Adam on float64 CPU tensors (same
+    definition, no weight decay, no amsgrad) over six steps of varying
+    gradients."""
+    import torch
+    rng = np.random.default_rng(3)
+    p = _rand_params(rng)
+    tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    opt = torch.optim.Adam(list(tp.values()), lr=5e-3, betas=(0.8, 0.95), eps=1e-7)
+    m = v = {k: np.zeros_like(x) for k, x in p.items()}
+    q = p
+    for t in range(1, 7):
+        g = _rand_params(rng)
+        for k in tp:
+            tp[k].grad = torch.tensor(g[k], dtype=torch.float64)
+        opt.step()
+        q, m, v = SG.adam_step(q, g, m, v, t, 5e-3, 0.8, 0.95, 1e-7)
+    for k in p:
+        np.testing.assert_allclose(q[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15)
