@@ -7,12 +7,18 @@ drawn (Philox) and evaluated (walk, eq. (2), HU and SU rebalancing, cost,
 gate), argmin, reconstruction and commit of the winner.  Inputs are seeded
 synthetic instances resident in HBM before the timed region.
 
-Prints one JSON line.  The roofline object prices the evaluation kernel's
-algorithmic integer operations per candidate against the integer VALU peak
-(the kernel is bound by VALU issue), with its algorithmic LDS bytes (the full
-walk) against the LDS peak and its measured HBM traffic against 8 TB/s beside
-it; the cpu_baseline object times the CPU oracle on a bounded sample of the
-same iteration's candidates.
+Prints one JSON line.  The default workload is the 500-field clustered
+instance (2^22 candidates per iteration).  The roofline object prices the
+evaluation kernel's algorithmic LDS bytes per candidate (one full evaluation:
+the walk of every tour, eq. (2), the units of the rebalancing rounds) against
+the LDS peak, over the evaluation launches of the very iterations that
+`value` times (the deterministic search is restarted and those iterations
+run again with HIP events around the launches); its integer-ALU figure and
+its measured HBM traffic sit beside it.  `full_search` covers every
+iteration of the workload's search from the initial solution.  The
+cpu_baseline object times the CPU oracle on a bounded sample of the same
+iteration's candidates; cpu_version runs the oracle's Algorithm 1, CPU
+version, against the GPU version's best cost on the 12-field instance.
 """
 import argparse
 import json
@@ -113,6 +119,61 @@ def cpu_baseline(inst, x0, n_sample):
     return dict(value=n_sample / dt, unit="evals/s", cores=procs, kind="oracle",
                 sample="first %d candidates of iteration 0 (seed 0, eps 0.5), %d processes, %.1f s"
                 % (n_sample, procs, dt), cpu_model=model)
+
+
+# Oracle candidates per cpu_baseline sample, per workload: about 10-30 s on
+# 16 host cores (clust500: about 5.6 ms per candidate on one core).
+CPU_SAMPLE = {"tiny12": 1 << 19, "mid100": 1 << 19, "clust500": 1 << 16}
+
+
+def cpu_version_baseline(budget_s=10.0):
+    """Algorithm 1's CPU version (one candidate per iteration, x_old <- x after
+    every draw) in the oracle, on the tiny12 instance, for `budget_s` seconds
+    of one host core: its evaluations per second, and when it first comes
+    within 1 % of, and first matches, the best cost of the GPU version's
+    search on the same instance (4096 candidates x 100 iterations, seed 0,
+    eps 0.5)."""
+    from oracle import search as S
+    from paper_1909_10286_amd import bl, inputs
+    from tests.gpu_common import from_csr
+    import torch
+
+    wl = inputs.WORKLOADS["tiny12"]
+    ctx = bl.Context(0)
+    ctx.set_stream(torch.cuda.current_stream())
+    inst = inputs.make_instance("tiny12", 0, accept=_accepting(ctx, bl))
+    iid = ctx.instance_upload(inst)
+    x0 = ctx.init_solution(iid)
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, 0)
+    thr = S.eps_threshold(0.5)
+    for _ in range(wl["iters"]):
+        ctx.search_step(iid, 0, thr, wl["n_cand"])
+    gpu_best = ctx.search_state(iid)["cost_best_m"]
+    ctx.close()
+    target = 1.01 * gpu_best
+    st = S.start(inst, from_csr(x0))
+    start_cost = st.cost_best
+    hits = {"target": None, "gpu_best": None}
+    t0 = time.perf_counter()
+    iters = 0
+    while time.perf_counter() - t0 < budget_s:
+        st = S.cpu_version_step(inst, st, 0, thr)
+        st.trace = []   # the harness keeps no trace: only the best cost is read
+        iters += 1
+        for k, c in (("target", target), ("gpu_best", gpu_best)):
+            if hits[k] is None and st.cost_best <= c:
+                hits[k] = (time.perf_counter() - t0, iters)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "algorithm": "Algorithm 1, CPU version (one candidate per iteration)",
+            "workload": "tiny12: %s, seed 0, eps 0.5" % DESCR["tiny12"], "cores": 1,
+            "evals_per_s": iters / dt, "iterations": iters, "seconds": dt,
+            "start_km": start_cost / 1e3, "gpu_version_best_km": gpu_best / 1e3, "target_km": target / 1e3,
+            "best_km": st.cost_best / 1e3,
+            "time_to_target_s": hits["target"] and hits["target"][0],
+            "iterations_to_target": hits["target"] and hits["target"][1],
+            "time_to_gpu_version_best_s": hits["gpu_best"] and hits["gpu_best"][0],
+            "iterations_to_gpu_version_best": hits["gpu_best"] and hits["gpu_best"][1]}
 
 
 def bench_batch(a):
@@ -424,11 +485,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="mid100", choices=sorted(DESCR) + ["batch256", "replica"])
+    ap.add_argument("--workload", default="clust500", choices=sorted(DESCR) + ["batch256", "replica"])
     ap.add_argument("--replica-seeds", type=int, default=10)
     ap.add_argument("--n", type=int, default=0, help="candidates per iteration (default: workload's)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
-                    help="candidates the oracle evaluates for cpu_baseline (2^19: about 12 s on 16 host cores)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="candidates the oracle evaluates for cpu_baseline (default: the workload's, "
+                         "about 10-30 s on 16 host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-screen", action="store_true",
                     help="skip the plain vs screened wall-time comparison")
@@ -457,61 +519,91 @@ def main():
         return bench_batch(a)
     if a.workload == "replica":
         return bench_replica(a)
+    return bench_search(a)
+
+
+def _replay(ctx, stream, iid, x0, seed, thr, n, warmup, steps, graph_chunk=0, timing=False):
+    """Searches from x0: `warmup` eager iterations, then `steps` timed ones,
+    replayed from a captured graph of `graph_chunk` iterations (eager when
+    0).  Returns (ms of the timed iterations from events on the library's
+    stream, evaluation-kernel ms and launches within them when `timing`)."""
+    import torch
+
+    from paper_1909_10286_amd import bl
+    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+    ctx.search_start(iid, warmup + steps)
+    for _ in range(warmup):
+        ctx.search_step(iid, seed, thr, n)
+    g = ctx.search_capture(iid, seed, thr, n, graph_chunk) if graph_chunk else None
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    if timing:
+        ctx.timing_read()
+        ctx.timing_enable(True)
+    e0.record(stream)
+    if g is not None:
+        for _ in range(steps // graph_chunk):
+            ctx.graph_launch(g)
+    else:
+        for _ in range(steps):
+            ctx.search_step(iid, seed, thr, n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kern = None
+    if timing:
+        kern = ctx.timing_read()
+        ctx.timing_enable(False)
+    return e0.elapsed_time(e1), kern
+
+
+def bench_search(a):
+    """One instance, Algorithm 1's GPU version on the device: `warmup`
+    eager iterations, then `steps` iterations timed (graph replays).  The
+    evaluation kernel's duration is taken over the same iterations: the
+    search is deterministic, so it is restarted from the initial solution,
+    the warm-up redone and the timed iterations run again eagerly with HIP
+    events around every evaluation launch."""
+    import torch
+
+    from paper_1909_10286_amd import bl, inputs
+
     wl = inputs.WORKLOADS[a.workload]
     n = a.n or wl["n_cand"]
     ctx = bl.Context(0)
     stream = torch.cuda.current_stream()
     ctx.set_stream(stream)
-
-    def accept(inst):
-        iid = ctx.instance_upload(inst)
-        try:
-            ctx.init_solution(iid)
-            return True
-        except bl.BlError as e:
-            if e.status == bl.EINFEASIBLE:
-                return False
-            raise
-    inst = inputs.make_instance(a.workload, 0, accept=accept)
+    inst = inputs.make_instance(a.workload, 0, accept=_accepting(ctx, bl))
     iid = ctx.instance_upload(inst)
     x0 = ctx.init_solution(iid)
-    ctx.solution_upload(iid, bl.SLOT_BASE, x0)
-    timing_steps = 10
-    ctx.search_start(iid, a.warmup + a.steps + timing_steps)
     seed, thr = 0, 1 << 31  # eps = 0.5
-    for _ in range(a.warmup):
-        ctx.search_step(iid, seed, thr, n)
-    # The timed iterations replay a captured graph of `chunk` iterations.
     chunk = 10 if a.steps % 10 == 0 else 1
-    g = ctx.search_capture(iid, seed, thr, n, chunk)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
     t0 = time.perf_counter()
-    for _ in range(a.steps // chunk):
-        ctx.graph_launch(g)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms, _ = _replay(ctx, stream, iid, x0, seed, thr, n, a.warmup, a.steps, graph_chunk=chunk)
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    # The evaluation kernel's own duration: HIP events around its launches in
-    # a few eager iterations after the timed region.
-    ctx.timing_read()
-    ctx.timing_enable(True)
-    for _ in range(timing_steps):
-        ctx.search_step(iid, seed, thr, n)
-    eval_ms, launches = ctx.timing_read()
-    ctx.timing_enable(False)
-    hbm_meas, lds_meas = ctx.measure_peaks()
     state = ctx.search_state(iid)
-    secs = ms / 1e3
-    value = n * a.steps / secs
-    per_launch_s = eval_ms / 1e3 / max(launches, 1)
+    # The same iterations again, eagerly, with the evaluation launches timed.
+    _, (eval_ms, launches) = _replay(ctx, stream, iid, x0, seed, thr, n, a.warmup, a.steps, timing=True)
+    again = ctx.search_state(iid)
+    # The whole search of the workload (every iteration from the initial
+    # solution), graph-replayed, and its evaluation launches timed the same way.
+    full_iters = wl["iters"]
+    fchunk = 10 if full_iters % 10 == 0 else 1
+    full_ms, _ = _replay(ctx, stream, iid, x0, seed, thr, n, 0, full_iters, graph_chunk=fchunk)
+    full_state = ctx.search_state(iid)
+    _, (full_eval_ms, full_launches) = _replay(ctx, stream, iid, x0, seed, thr, n, 0, full_iters,
+                                               timing=True)
+    hbm_meas, lds_meas = ctx.measure_peaks()
+    ctx.close()
+
+    value = n * a.steps / (ms / 1e3)
+    step_s = eval_ms / 1e3 / max(launches, 1)   # one evaluation step (a lane kernel's two passes)
     bpc = lds_bytes_per_candidate(inst.n_fields, inst.n_bps, inst.n_tours, inst.n_hus, inst.n_sus)
-    achieved = bpc * n / per_launch_s / 1e9
-    alu = ALU_OPS_PER_CANDIDATE[a.workload] * n / per_launch_s / 1e12
+    achieved = bpc * n / step_s / 1e9
+    ops = ALU_OPS_PER_CANDIDATE.get(a.workload)
     traffic = recorded_traffic(a.workload) if n == wl["n_cand"] else None
+    full_step_s = full_eval_ms / 1e3 / max(full_launches, 1)
+    kernel = ("k_eval_lane" if inst.n_tours <= LANE_MAX_TOURS else "k_eval") + " (search mode)"
     out = {
         "metric": "candidate evals/s",
         "value": value,
@@ -528,28 +620,35 @@ def main():
         "config": {"workload": "%s: %s, %d candidates/iteration" % (a.workload, DESCR[a.workload], n),
                    "n_candidates": n, "instance_seed": 0, "search_seed": seed, "eps": 0.5,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": alu / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": ("k_eval_lane" if inst.n_tours <= LANE_MAX_TOURS else "k_eval") + " (search mode)",
-                     "ops_per_candidate": ALU_OPS_PER_CANDIDATE[a.workload],
-                     "kernel_ms_per_launch": per_launch_s * 1e3,
-                     "lds": {"achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / LDS_PEAK_GBS, "bytes_per_candidate": bpc,
-                             "peak_measured": lds_meas, "frac_measured": achieved / lds_meas},
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "kernel": kernel, "bytes_per_candidate": bpc,
+                     "kernel_ms_per_launch": step_s * 1e3,
+                     "launches_timed": launches,
+                     "same_iterations_as_value": again["cost_best_m"] == state["cost_best_m"]
+                     and again["it"] == state["it"],
+                     "peak_measured": lds_meas, "frac_measured": achieved / lds_meas,
+                     "alu": None if ops is None else {
+                         "achieved": ops * n / step_s / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                         "frac": ops * n / step_s / 1e12 / ALU_PEAK_TOPS, "ops_per_candidate": ops},
                      "hbm": None if traffic is None else {
-                         "achieved": traffic / per_launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": traffic / per_launch_s / 1e9 / HBM_PEAK_GBS,
-                         "peak_measured": hbm_meas, "frac_measured": traffic / per_launch_s / 1e9 / hbm_meas}},
+                         "achieved": traffic / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": traffic / step_s / 1e9 / HBM_PEAK_GBS,
+                         "peak_measured": hbm_meas, "frac_measured": traffic / step_s / 1e9 / hbm_meas}},
         "measured_peaks": {"hbm_copy_gbs": hbm_meas, "lds_read_gbs": lds_meas},
         "search": {"cost_best_km": state["cost_best_m"] / 1000.0, "t_best_h": state["t_best_s"] / 3600.0,
                    "iterations": state["it"], "wall_s": wall},
+        "full_search": {"iterations": full_iters, "value": n * full_iters / (full_ms / 1e3),
+                        "ms_per_step": full_ms / full_iters, "kernel_ms_per_launch": full_step_s * 1e3,
+                        "lds_frac": bpc * n / full_step_s / 1e9 / LDS_PEAK_GBS,
+                        "cost_best_km": full_state["cost_best_m"] / 1000.0},
     }
-    ctx.close()
-    if not a.no_screen and a.workload == "mid100":
+    if not a.no_screen and a.workload == "clust500":
         out["screen"] = screen_comparison()
     if not a.no_cpu_baseline:
         from tests.gpu_common import from_csr
-        out["cpu_baseline"] = cpu_baseline(inst, from_csr(x0), a.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(inst, from_csr(x0), a.cpu_sample or CPU_SAMPLE[a.workload])
+        out["cpu_version"] = cpu_version_baseline()
     print(json.dumps(out), flush=True)
 
 

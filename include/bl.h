@@ -197,8 +197,13 @@ bl_status bl_evaluate_batch(bl_ctx *ctx, int32_t inst, const uint64_t *d_moves, 
                             int64_t t_star_s, uint64_t *d_key, float *d_cost_km,
                             int32_t *d_makespan_s, uint8_t *d_flags);
 
-/* Minimum of n keys into *d_best (device).  The smallest index wins ties
- * because keys carry the index.  Async. */
+/* The argmin of Algorithm 1's GPU version (sec. 2.5): the minimum of n keys
+ * from bl_evaluate_batch into *d_best (device), i.e. the cheapest candidate
+ * that is feasible (eq. (2)) and not discarded by the makespan gate, or
+ * BL_INF_KEY when there is none.  The smallest index wins ties because keys
+ * carry the index.  d_key: n device keys (not read when n = 0); d_best: one
+ * device u64, caller-owned.  BL_EINVAL for a null d_best, or a null d_key
+ * with n > 0.  Async on the context's stream. */
 bl_status bl_select_best(bl_ctx *ctx, const uint64_t *d_key, uint32_t n, uint64_t *d_best);
 
 /* Start of Algorithm 1: evaluate the base slot with the gate off, store its minimised units
