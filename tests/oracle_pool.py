@@ -21,6 +21,15 @@ def _results(args):
     return out
 
 
+def _results_at(args):
+    job, idx = args
+    out = []
+    for i in idx:
+        _, r = S.candidate(job, int(i))
+        out.append((r.key, r.cost_km, r.makespan_s, r.flags))
+    return out
+
+
 def n_procs():
     try:
         n = len(os.sched_getaffinity(0))
@@ -49,6 +58,21 @@ class OraclePool:
         for part in self._pool.map(_results, self._chunks(job, n, lo)):
             out += part
         return out
+
+    def results_at(self, job, idx):
+        """(key, cost km, makespan s, flags) of the candidates with the given
+        indices, in that order."""
+        idx = [int(i) for i in idx]
+        step = max(1, len(idx) // (self.procs * 4))
+        out = []
+        for part in self._pool.map(_results_at, [(job, idx[a:a + step]) for a in range(0, len(idx), step)]):
+            out += part
+        return out
+
+    def results_multi(self, pairs):
+        """For each (job, indices) pair, the results of those candidates (as
+        results_at), one pair per task."""
+        return self._pool.map(_results_at, [(job, [int(i) for i in idx]) for job, idx in pairs])
 
     def close(self):
         self._pool.terminate()

@@ -9,6 +9,7 @@ import pytest
 
 from oracle import init as OI
 from oracle import model as M
+from oracle import moves as MV
 from oracle import search as S
 from paper_1909_10286_amd import bl, inputs
 
@@ -171,3 +172,53 @@ def test_search_graph_replays_match_eager(ctx):
     replays = run(True)
     for r, rows in enumerate(replays):
         assert rows == eager[:3 * (r + 1)]
+
+
+def test_batch256_full_size_sampled(ctx, pool):
+    """The batched workload at its full size: all 256 members, 2^16
+    candidates each, two iterations, every class at 4096 candidates per work
+    item (the largest tile the autotuner tries), so that a work item defers
+    more long SU tails than its LDS queue holds and finishes the rest in
+    place.  The oracle does not redo the argmin over 2^16 candidates per
+    member: per member and iteration it re-evaluates the winner (its key must
+    be the iteration's) and 64 sampled candidates (none may beat it), then
+    takes the step with that winner, so that the trajectories, x* and x_old
+    after both iterations are compared in full."""
+    _say("batch256 full size")
+    K, n, iters, seed, thr = 256, 1 << 16, 2, 4, S.eps_threshold(0.5)
+    insts, ids, x0s = _members(ctx, range(K))
+    b = ctx.batch_create(ids, n)
+    ctx.batch_set_schedule(b, [4096, 4096, 4096], 0)
+    ctx.batch_start(b, iters)
+    for _ in range(iters):
+        ctx.batch_step(b, seed, thr)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    states = [S.start(inst, x0) for inst, x0 in zip(insts, x0s)]
+    rows = [ctx.search_trace(iid) for iid in ids]
+    assert all(len(r) == iters for r in rows)
+    for it in range(iters):
+        jobs, idx = [], []
+        for k, (inst, st) in enumerate(zip(insts, states)):
+            base = st.x_best if MV.exploit_draw(seed, it, k, thr) else st.x_old
+            jobs.append((inst, base, seed, it, k, False, M.GATE_LE, st.t_best, None, True))
+            idx.append(rng.choice(n, 64, replace=False))
+        sampled = pool.results_multi(list(zip(jobs, idx)))
+        for k, inst in enumerate(insts):
+            key = int(rows[k][it]["best_key"])
+            assert min(r[0] for r in sampled[k]) >= key, (k, it)
+            keys = [M.INF_KEY] * n
+            if key != bl.INF_KEY:
+                i_star = key & 0xFFFFFF
+                assert S.candidate(jobs[k], i_star)[0] == key, (k, it)
+                keys[i_star] = key
+            states[k] = S.step(inst, states[k], seed, n, thr, inst_idx=k,
+                               map_fn=lambda job, n_all, keys=keys: keys)
+    n_improved = 0
+    for k, (iid, st) in enumerate(zip(ids, states)):
+        assert [(r["it"], r["best_key"], r["cost_m"], r["indicator"], bool(r["use_best"])) for r in rows[k]] == \
+            [(r.it, r.best_key, r.cost_m, r.indicator, r.use_best) for r in st.trace], k
+        assert from_csr(ctx.solution_download(iid, bl.SLOT_BEST)) == st.x_best, k
+        assert from_csr(ctx.solution_download(iid, bl.SLOT_OLD)) == st.x_old, k
+        n_improved += sum(r.indicator != 0 for r in st.trace)
+    assert n_improved > K // 2

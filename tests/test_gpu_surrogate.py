@@ -1,6 +1,7 @@
 """The learned screen on the GPU (bf16 MFMA, fp32 accumulation) against the
-float64 reference in oracle/surrogate.py: predictions, summed gradients, and
-that Adam steps on the GPU reduce the loss."""
+float64 reference in oracle/surrogate.py: predictions, summed gradients
+element by element within their bf16 rounding bound, Adam steps against the
+oracle's, and that training on the GPU reduces the loss."""
 import sys
 
 import numpy as np
@@ -11,7 +12,8 @@ from oracle import moves as MV
 from oracle import surrogate as SG
 from paper_1909_10286_amd import bl
 
-from .sur_common import draw_moves as _moves, flat as _flat, setup, unflat as _unflat
+from .sur_common import draw_moves as _moves, flat as _flat, rounding_model_gradient, setup, \
+    unflat as _unflat
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +25,8 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _setup(ctx, name, wseed=3):
-    inst, st, iid, sur, p, sc = setup(ctx, name, wseed)
+def _setup(ctx, name, wseed=3, max_examples=512):
+    inst, st, iid, sur, p, sc = setup(ctx, name, wseed, max_examples)
     return inst, st.x_best, iid, sur, p, sc
 
 
@@ -49,33 +51,121 @@ def test_predict_matches_float64_reference(ctx, name):
     assert np.corrcoef(rp, gp)[0, 1] > 0.98
 
 
-@pytest.mark.parametrize("name", ["tiny12", "mid100"])
-def test_gradients_match_float64_reference(ctx, name):
-    _say("surrogate gradients", name)
-    inst, base, iid, sur, p, sc = _setup(ctx, name)
-    mvs = _moves(inst, base, 48, seed=11)
+# Draws of the rounding model per test, and the multiple of its standard
+# deviation that an element's error may reach.  With 12 draws the estimated
+# deviation is within a factor 0.5..1.5 of the true one (95 %); a device error
+# within 4 true deviations then stays below 8 estimated ones.  (The float64
+# gradient at the bf16-rounded weights and features, the rounding the device
+# actually does, lies within 5.4 estimated deviations on these cases.)
+MODEL_DRAWS = 12
+MODEL_SIGMAS = 8.0
+
+
+def _reference(ctx, inst, base, p, sc, mvs):
+    """Summed float64 loss and gradient over the moves, the per-element
+    rounding bound (MODEL_SIGMAS standard deviations of the summed gradient
+    under the bf16 rounding model), and the device buffers of the examples."""
     cost, mk = [], []
     gref = {k: np.zeros(s) for k, s in bl.SUR_SHAPES}
+    draws = [{k: np.zeros(s) for k, s in bl.SUR_SHAPES} for _ in range(MODEL_DRAWS)]
+    keys = [0x5EED0000 + 7919 * j for j in range(MODEL_DRAWS)]   # one rounding function per draw
     lref = 0.0
     for m in mvs:
-        ev = M.evaluate_solution(inst, MV.apply_move(base, m))
+        sol = MV.apply_move(base, m)
+        ev = M.evaluate_solution(inst, sol)
         cost.append(ev.cost_m / 1000.0)
         mk.append(ev.makespan_s)
-        l, g = SG.example_loss_and_grad(p, inst, MV.apply_move(base, m), sc, ev.cost_m, ev.makespan_s)
+        l, g = SG.example_loss_and_grad(p, inst, sol, sc, ev.cost_m, ev.makespan_s)
         lref += l
         for k in gref:
             gref[k] += g[k]
+        for j in range(MODEL_DRAWS):
+            gj = rounding_model_gradient(p, inst, sol, sc, ev.cost_m, ev.makespan_s, keys[j])
+            for k in gref:
+                draws[j][k] += gj[k]
+    bound = {}
+    for k in gref:
+        sig = np.sqrt(np.mean([(d[k] - gref[k]) ** 2 for d in draws], axis=0))
+        bound[k] = MODEL_SIGMAS * sig + 1e-9 * np.abs(gref[k]).max()
     words = np.array([MV.encode(m) for m in mvs], dtype=np.uint64)
     d_mv = torch.from_numpy(words.view(np.int64)).cuda()
     d_c = torch.tensor(cost, dtype=torch.float32, device="cuda")
     d_m = torch.tensor(mk, dtype=torch.int32, device="cuda")
+    return lref, gref, bound, (d_mv, d_c, d_m)
+
+
+# n examples of `name`: tiny12 and mid100 at 48 (one row chunk per
+# workgroup); mid100 at 131 (13100 field rows, 410 chunks of 32 rows with a
+# ragged last one: every backward workgroup takes two chunks, the second
+# loaded while the first is on MFMA).
+@pytest.mark.parametrize("name,n", [("tiny12", 48), ("mid100", 48), ("mid100", 131)])
+def test_gradients_match_float64_reference(ctx, name, n):
+    """Every element of the summed gradient (bf16 MFMA, fp32 accumulation)
+    within its rounding bound of the float64 gradient: MODEL_SIGMAS standard
+    deviations of that element under the bf16 rounding model (a relative
+    perturbation of up to 2^-8 at every operand the kernels round)."""
+    _say("surrogate gradients", name, n)
+    inst, base, iid, sur, p, sc = _setup(ctx, name, max_examples=max(n, 64))
+    mvs = _moves(inst, base, n, seed=11)
+    lref, gref, bound, (d_mv, d_c, d_m) = _reference(ctx, inst, base, p, sc, mvs)
     g, loss = ctx.sur_gradients(sur, d_mv, d_c, d_m, len(mvs))
     gg = _unflat(g)
     assert loss == pytest.approx(lref, rel=3e-2)
+    worst = {}
     for k, _ in bl.SUR_SHAPES:
-        den = np.linalg.norm(gref[k])
-        rel = np.linalg.norm(gg[k] - gref[k]) / max(den, 1e-12)
-        assert rel <= 6e-2, (k, rel, den)
+        tol = bound[k]
+        err = np.abs(gg[k] - gref[k])
+        worst[k] = float((err / tol).max())
+        bad = np.argwhere(err > tol)
+        assert bad.size == 0, (k, bad[:5].tolist(), gg[k][tuple(bad[0])], gref[k][tuple(bad[0])],
+                               tol[tuple(bad[0])])
+    _say("largest error / bound per block:", {k: round(v, 3) for k, v in worst.items()})
+
+
+def test_adam_step_matches_oracle(ctx):
+    """bl_sur_train_step from known weights against the oracle's Adam
+    (Kingma and Ba 2015) on the mean gradient, element by element: (a) on the
+    device's own mean gradient, to float32 rounding, for two steps (the
+    second exercises the moment state and the bias corrections); (b) for the
+    first step, on the float64 gradient: the first update is
+    lr g / (|g| + eps), increasing in g, so the device's weight must lie
+    between the updates for g -/+ the gradient's rounding bound."""
+    _say("surrogate adam")
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    inst, base, iid, sur, p, sc = _setup(ctx, "mid100", max_examples=64)
+    mvs = _moves(inst, base, 40, seed=13)
+    n = len(mvs)
+    _, gref, gbound, (d_mv, d_c, d_m) = _reference(ctx, inst, base, p, sc, mvs)
+    w0 = _flat(p)
+    g1 = np.asarray(ctx.sur_gradients(sur, d_mv, d_c, d_m, n)[0], dtype=np.float64)
+    ctx.sur_train_step(sur, d_mv, d_c, d_m, n)
+    w1 = np.asarray(ctx.sur_get_weights(sur), dtype=np.float64)
+    g2 = np.asarray(ctx.sur_gradients(sur, d_mv, d_c, d_m, n)[0], dtype=np.float64)
+    ctx.sur_train_step(sur, d_mv, d_c, d_m, n)
+    w2 = np.asarray(ctx.sur_get_weights(sur), dtype=np.float64)
+    P0 = {"w": w0.astype(np.float64)}
+    zero = {"w": np.zeros_like(P0["w"])}
+    pa, ma, va = SG.adam_step(P0, {"w": g1 / n}, zero, zero, 1, lr, b1, b2, eps)
+    pb, _, _ = SG.adam_step({"w": w1}, {"w": g2 / n}, ma, va, 2, lr, b1, b2, eps)
+    # float32 arithmetic of one update: the weight's rounding, and the
+    # lr-sized step to the relative error of float32 bias corrections
+    # (1 - 0.999 in float32 is 1.3e-5 off, 6.4e-6 under the square root).
+    step_tol = 3e-5 * lr
+    for got, want, prev in ((w1, pa["w"], w0), (w2, pb["w"], w1)):
+        tol = 2.0 ** -23 * np.abs(prev) + step_tol
+        assert np.all(np.abs(got - want) <= tol), np.abs(got - want).max()
+    # (b): the first step against the float64 gradient.
+    gr = np.concatenate([gref[k].reshape(-1) for k, _ in bl.SUR_SHAPES]) / n
+    bound = np.concatenate([gbound[k].reshape(-1) for k, _ in bl.SUR_SHAPES]) / n
+    lo = P0["w"] - lr * (gr + bound) / (np.abs(gr + bound) + eps)
+    hi = P0["w"] - lr * (gr - bound) / (np.abs(gr - bound) + eps)
+    slack = 2.0 ** -23 * np.abs(P0["w"]) + step_tol
+    assert np.all(w1 >= lo - slack) and np.all(w1 <= hi + slack)
+    # Where the gradient's sign is certain, the step is lr in size, against it.
+    sure = np.abs(gr) > 2 * bound
+    _say("parameters with a certain gradient sign: %.3f" % sure.mean())
+    assert sure.mean() > 0.2, sure.mean()
+    assert np.all(np.sign(P0["w"][sure] - w1[sure]) == np.sign(gr[sure]))
 
 
 def test_adam_steps_reduce_loss(ctx):

@@ -139,3 +139,51 @@ def test_adam_matches_torch_optimizer():
         q, m, v = SG.adam_step(q, g, m, v, t, 5e-3, 0.8, 0.95, 1e-7)
     for k in p:
         np.testing.assert_allclose(q[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def _bf16(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_rounding_model_gradient():
+    """The error model behind the GPU gradient tolerance.  Without
+    perturbation it is the oracle's gradient (its factoring, rows projected
+    by W3 before pooling, is the same function).  Its spread covers the
+    rounding the device certainly does: the float64 gradient at the
+    bf16-rounded W1, W2, W3 rows and features stays within 8 estimated
+    standard deviations of the unrounded one, element by element."""
+    from oracle import moves as MV
+
+    from .sur_common import draw_moves, flat, rounding_model_gradient, unflat
+    inst, _, sc = _setup("tiny12")
+    st = S.start(inst, OI.init_solution(inst))
+    p = SG.init_params(inputs.surrogate_init_words(3))
+    rng = np.random.default_rng(3)
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    p = unflat(flat(p))
+    pw = dict(p, W1=_bf16(p["W1"]), W2=_bf16(p["W2"]))
+    pw["W3"] = np.concatenate([_bf16(p["W3"][:SG.D_H]), p["W3"][SG.D_H:]])
+    keys = [0x5EED0000 + 7919 * j for j in range(12)]
+    g0, g1, draws = {}, {}, [{} for _ in keys]
+
+    def add(acc, g):
+        for k in g:
+            acc[k] = acc.get(k, 0) + g[k]
+    for mv in draw_moves(inst, st.x_best, 24, seed=11):
+        sol = MV.apply_move(st.x_best, mv)
+        ev = M.evaluate_solution(inst, sol)
+        _, g = SG.example_loss_and_grad(p, inst, sol, sc, ev.cost_m, ev.makespan_s)
+        add(g0, g)
+        gm = rounding_model_gradient(p, inst, sol, sc, ev.cost_m, ev.makespan_s)
+        for k in g:
+            np.testing.assert_allclose(gm[k], g[k], rtol=1e-10, atol=1e-12 * np.abs(g[k]).max())
+        phi, u, fbp, btour, active = SG.features(inst, sol, sc)
+        P, Mk, c = SG.forward(pw, _bf16(phi), u, fbp, btour, active, inst.n_bps)
+        add(g1, SG.backward(pw, c, P, Mk, ev.cost_m / sc.c0, ev.makespan_s / sc.t0))
+        for d, key in zip(draws, keys):
+            add(d, rounding_model_gradient(p, inst, sol, sc, ev.cost_m, ev.makespan_s, key))
+    for k in g0:
+        sig = np.sqrt(np.mean([(d[k] - g0[k]) ** 2 for d in draws], axis=0))
+        assert np.all(np.abs(g1[k] - g0[k]) <= 8.0 * sig + 1e-9 * np.abs(g0[k]).max()), k
