@@ -112,8 +112,35 @@ __device__ __forceinline__ uint32_t defer_slot(bool deferred, uint32_t *cnt) {
   return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(dmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dmask, 0u));
 }
 
+// Orders LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void lane_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Candidates a wave holds back between its feasibility checks and their
+// evaluation: up to 63 left over plus one batch of 64.
+constexpr int kLaneQueue = 128;
+
+// Per-candidate outputs of the batch and gather modes.
+template <int MODE>
+__device__ __forceinline__ void lane_write(uint32_t c, const CandResult &r, uint64_t *out_key, float *out_cost,
+                                           int32_t *out_mk, uint8_t *out_flags) {
+  if (MODE == kModeSearch) return;
+  if (out_key) out_key[c] = r.key;
+  if (out_cost) out_cost[c] = r.cost_km;
+  if (out_mk) out_mk[c] = r.mk;
+  if (out_flags) out_flags[c] = (uint8_t)r.flags;
+}
+
+// Waves per SIMD the lane kernel is compiled for: 2 (at most 256 VGPRs).
+// Left to itself the compiler takes 264 registers at 10 tours and drops to
+// one wave (clust500: 1.72 ms per evaluation step against 1.19 ms bounded);
+// at 5 tours, 3 waves (168 VGPRs, a few spills) measured 2 % slower than 2.
+constexpr int kLaneWaves = 2;
+
 template <int N, bool SMALL, int MODE>
-__global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, const uint64_t *__restrict__ moves,
+__global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int phase, const uint64_t *__restrict__ moves,
                                                    uint32_t n, int64_t t_star_arg, uint64_t seed,
                                                    uint32_t inst_index, uint64_t *__restrict__ out_key,
                                                    float *__restrict__ out_cost,
@@ -127,13 +154,15 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, cons
   const uint32_t total = phase == 0 ? n : min(*P.defer_cnt, P.defer_cap);
   if (phase == 1 && blockIdx.x * blockDim.x >= total) return;
   __shared__ LaneBase s_base;
+  __shared__ uint64_t s_qw[4][kLaneQueue];
+  __shared__ uint32_t s_qc[4][kLaneQueue];
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   stage(lds, P.image, P.lay.total_words);
   __syncthreads();
   // The distance matrix stays in global memory: a candidate reads at most a
   // few legs of it.
   const View V = make_view(lds, P.lay, P.dist);
-  lane_base_fill(s_base, V, N);
+  lane_base_fill(s_base, V, P, N);
   __syncthreads();
   uint32_t it = 0;
   int64_t t_star = t_star_arg;
@@ -143,42 +172,85 @@ __global__ __launch_bounds__(256) void k_eval_lane(InstParams P, int phase, cons
   }
   const int su_limit = phase == 0 && P.defer_cap ? su_defer_rounds(N) : 0;
   uint64_t best = kInfKey;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const uint32_t c = phase == 0 ? i : P.defer[i];
+  // Full evaluation of feasible candidate c (move word w).  A candidate
+  // whose SU rounds pass su_limit goes to the deferred list; when the list
+  // is full it is evaluated again here with no limit (one copy of the
+  // evaluation in the code, run once or twice).
+  auto evaluate = [&](uint32_t c, uint64_t w) {
     const uint32_t ci = MODE == kModeGather ? gather[c] : c;
-    const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
     const Move m = decode_move(w, V, P);
     CandResult r{kInfKey, __builtin_inff(), 0x7FFFFFFF, 0u};
-    if (!m.valid) {
-      r.flags = kCandInvalid;
-    } else {
-      LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, su_limit);
+    LaneOut o;
+    for (int lim = su_limit;; lim = 0) {
+      o = eval_lane<N, SMALL>(V, P, s_base, m, lim);
       const uint32_t slot = defer_slot<su_defer_rounds(N) == 1>(o.deferred, P.defer_cnt);
-      if (o.deferred) {
-        if (slot < P.defer_cap) {
-          P.defer[slot] = c;
-          continue;
-        }
-        o = eval_lane<N, SMALL>(V, P, s_base, m, 0);   // no room: finish here
-      }
-      r.flags = o.flags;
-      if (o.feasible) {
-        r.cost_km = (float)((double)o.cost / 1000.0);
-        r.mk = o.makespan >= 0x7FFFFFFFll ? 0x7FFFFFFF : (int32_t)o.makespan;
-        if (is_gated(o.makespan, t_star, P.flags))
-          r.flags |= kCandGated;
-        else
-          r.key = (o.cost << 24) | (uint64_t)ci;
+      if (!o.deferred) break;
+      if (slot < P.defer_cap) {
+        P.defer[slot] = c;
+        return;
       }
     }
-    if (MODE != kModeSearch) {
-      if (out_key) out_key[c] = r.key;
-      if (out_cost) out_cost[c] = r.cost_km;
-      if (out_mk) out_mk[c] = r.mk;
-      if (out_flags) out_flags[c] = (uint8_t)r.flags;
+    r.flags = o.flags;
+    if (o.feasible) {
+      r.cost_km = (float)((double)o.cost / 1000.0);
+      r.mk = o.makespan >= 0x7FFFFFFFll ? 0x7FFFFFFF : (int32_t)o.makespan;
+      if (is_gated(o.makespan, t_star, P.flags))
+        r.flags |= kCandGated;
+      else
+        r.key = (o.cost << 24) | (uint64_t)ci;
     }
+    lane_write<MODE>(c, r, out_key, out_cost, out_mk, out_flags);
     best = r.key < best ? r.key : best;
+  };
+  // Each wave checks 64 candidates at a time for validity and eq. (2) (the
+  // others get their outputs at once) and queues the feasible ones in LDS;
+  // whenever 64 are queued, every lane evaluates one.  About half the
+  // candidates break eq. (2); without the queue their lanes would idle
+  // through the rebalancing rounds of the feasible ones.  In the second
+  // pass the candidates are the deferred list's, all feasible.
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t *qw = s_qw[wave];
+  uint32_t *qc = s_qc[wave];
+  uint32_t qn = 0;   // wave-uniform
+  const uint32_t wstride = gridDim.x * (blockDim.x >> 6) * 64u;
+  for (uint32_t i0 = (blockIdx.x * (blockDim.x >> 6) + (uint32_t)wave) * 64u;; i0 += wstride) {
+    const bool more = i0 < total;
+    if (more) {
+      const uint32_t i = i0 + (uint32_t)lane;
+      bool feas = false;
+      uint64_t w = 0;
+      uint32_t c = 0;
+      if (i < total) {
+        c = phase == 0 ? i : P.defer[i];
+        const uint32_t ci = MODE == kModeGather ? gather[c] : c;
+        w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
+        const Move m = decode_move(w, V, P);
+        CandResult r{kInfKey, __builtin_inff(), 0x7FFFFFFF, 0u};
+        if (!m.valid)
+          r.flags = kCandInvalid;
+        else if (!delta_feasible(V, m))
+          r.flags = kCandInfeasible;
+        else
+          feas = true;
+        if (!feas) lane_write<MODE>(c, r, out_key, out_cost, out_mk, out_flags);
+      }
+      const uint64_t bal = __ballot(feas);
+      if (feas) {
+        const uint32_t at = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        qw[at] = w;
+        qc[at] = c;
+      }
+      qn += (uint32_t)__popcll(bal);
+    }
+    while (qn >= 64u || (!more && qn > 0u)) {
+      lane_wave_sync();
+      const uint32_t take = qn < 64u ? qn : 64u;
+      if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane]);
+      lane_wave_sync();
+      qn -= take;
+    }
+    if (!more) break;
   }
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
@@ -642,7 +714,7 @@ __global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
     if ((int)k != cur) {   // uniform over the workgroup
       stage(lds, P.image, P.lay.total_words);
       __syncthreads();
-      lane_base_fill(s_base, V, P.NT);
+      lane_base_fill(s_base, V, P, P.NT);
       cur = (int)k;
     }
     __syncthreads();

@@ -25,28 +25,56 @@ using tm_t = int32_t;
 constexpr tm_t kTInf = INT32_MAX, kTNegInf = INT32_MIN;
 
 // Base values per tour, the same for every candidate of a launch (one copy
-// per workgroup in LDS): rate sum of the tour's HUs and fill-time sum of its
-// SUs.
+// per workgroup in LDS): rate sum of the tour's HUs, fill-time sum of its
+// SUs, its critical SU, and its road time, completion time and waiting time
+// with the base's units.  A move changes two tours; every other tour of a
+// candidate starts from these values, and its waiting time stays the
+// base's unless the HU rebalancing moves one of its HUs.
 struct LaneBase {
   uint32_t R[kLaneMaxTours];
   uint32_t load[kLaneMaxTours];
+  int32_t top[kLaneMaxTours];  // critical SU (largest fill time) of the base, -1 without SUs
+  uint32_t lc[kLaneMaxTours];  // floor(3600 L / v_HU)
+  tm_t T[kLaneMaxTours];       // completion time (0 for an inactive tour)
+  tm_t W[kLaneMaxTours];       // waiting time, eq. (5) (0 for an inactive tour)
   double rcp[kMaxHus + 1];   // rcp[k] = 1/k (k >= 1): the reciprocals udiv_small takes
 };
 
-// Fills the per-tour sums of `B` for the tours 0..nt-1 of the base in V (zero
+__device__ __forceinline__ tm_t lane_tcompl(uint32_t lc, uint32_t A, uint32_t rate) {
+  return rate == 0 ? kTInf : (tm_t)(lc + (uint32_t)udiv(3600ull * A, rate));
+}
+
+// Fills `B` for the tours 0..nt-1 of the base in V (zero and inactive
 // beyond), and the reciprocal table.  Called by a whole workgroup; the caller
 // synchronises before and after.
-__device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, int nt) {
+__device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const InstParams &P, int nt) {
   if (threadIdx.x < kLaneMaxTours) {
     const int t = threadIdx.x;
-    uint32_t R = 0, ld = 0;
+    uint32_t R = 0, ld = 0, lc = 0, nhu = 0;
+    int top = -1;
+    tm_t T = 0, W = 0;
     if (t < nt) {
-      for (uint64_t mm = V.hu_mask[t]; mm; mm &= mm - 1) R += V.hu_rate[__ffsll((unsigned long long)mm) - 1];
+      for (uint64_t mm = V.hu_mask[t]; mm; mm &= mm - 1) {
+        R += V.hu_rate[__ffsll((unsigned long long)mm) - 1];
+        ++nhu;
+      }
       M128 sm{V.su_mask[2 * t], V.su_mask[2 * t + 1]};
+      if (!m_empty(sm)) top = m_top(sm);
       while (!m_empty(sm)) ld += V.su_fill[m_pop_low(sm)];
+      lc = (uint32_t)udiv(3600ull * V.t_len[t], P.v_hu);
+      if ((int)V.t_end[t] > (int)V.t_start[t]) {
+        T = lane_tcompl(lc, V.t_area[t], R);
+        const uint32_t mc = V.t_mcnt[t], dm = mc ? V.t_msum[t] / mc : 0u;
+        W = (top < 0 || nhu == 0) ? kTInf
+                                  : (tm_t)udiv(7200ull * dm, V.su_speed[top]) - (tm_t)udiv(ld - V.su_fill[top], nhu);
+      }
     }
     B.R[t] = R;
     B.load[t] = ld;
+    B.top[t] = top;
+    B.lc[t] = lc;
+    B.T[t] = T;
+    B.W[t] = W;
   }
   for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) B.rcp[k] = k ? 1.0 / (double)k : 0.0;
 }
@@ -140,10 +168,6 @@ __device__ __forceinline__ Change move_change(const View &V, const InstParams &P
     c.mc_d = 1;
   }
   return c;
-}
-
-__device__ __forceinline__ tm_t lane_tcompl(uint32_t lc, uint32_t A, uint32_t rate) {
-  return rate == 0 ? kTInf : (tm_t)(lc + (uint32_t)udiv(3600ull * A, rate));
 }
 
 __device__ __forceinline__ tm_t lane_twait(const View &V, const LaneBase &B, const M128 &msk, uint32_t ld,
@@ -290,13 +314,26 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   }
   const bool embedded = !(P.flags & kNoEmbeddedMin);
   // ---- HU min-max rebalancing: completion time ----
+  // Every tour but the move's two keeps the base's road and completion times.
   uint32_t lc[N];
   tm_t T[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    lc[t] = (uint32_t)udiv(3600ull * L[t], P.v_hu);
-    T[t] = ((actm >> t) & 1u) ? lane_tcompl(lc[t], A[t], R[t]) : 0;
+    lc[t] = B.lc[t];
+    T[t] = B.T[t];
   }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int g = j == 0 ? ch.Ts : ch.Td;
+    const uint32_t lcg = (uint32_t)udiv(3600ull * lpick(L, g), P.v_hu);
+    const tm_t Tg = ((actm >> g) & 1u) ? lane_tcompl(lcg, lpick(A, g), B.R[g]) : 0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      lc[t] = t == g ? lcg : lc[t];
+      T[t] = t == g ? Tg : T[t];
+    }
+  }
+  uint32_t hu_moved = 0;   // tours whose HUs the rounds changed
   if (embedded) {
     int rounds = 0;
     while (true) {
@@ -348,16 +385,32 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         T[t] = keep ? Tn[t] : T[t];
       }
       if (!keep) break;
+      hu_moved |= (1u << gmin) | (1u << gmax);
     }
   }
   const tm_t tmax = lane_max(T, actm);
   // ---- SU min-max rebalancing, Alg. 2: waiting time ----
+  // Waiting times: the base's, but for the move's two tours and the tours
+  // whose HU count the rounds changed.  The SU masks are still the base's,
+  // so a tour's critical SU and fill-time sum are the base's.
   uint32_t nhu[N];
   tm_t W[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     nhu[t] = (uint32_t)lane_popc(hm[t]);
-    W[t] = ((actm >> t) & 1u) ? lane_twait(V, B, sm[t], load[t], nhu[t], dm[t]) : 0;
+    W[t] = B.W[t];
+  }
+  for (uint32_t redo = hu_moved | (1u << ch.Ts) | (1u << ch.Td); redo; redo &= redo - 1) {
+    const int g = lane_ffs(redo) - 1;
+    const uint32_t nh = lpick(nhu, g);
+    const int s = B.top[g];
+    tm_t Wg = 0;
+    if ((actm >> g) & 1u)
+      Wg = (s < 0 || nh == 0) ? kTInf
+                              : (tm_t)udiv(7200ull * lpick(dm, g), V.su_speed[s]) -
+                                    (tm_t)udiv_small(B.load[g] - V.su_fill[s], nh, B.rcp[nh]);
+#pragma unroll
+    for (int t = 0; t < N; ++t) W[t] = t == g ? Wg : W[t];
   }
   if (embedded) {
     int rounds = 0;
