@@ -197,6 +197,23 @@ bl_status bl_evaluate_batch(bl_ctx *ctx, int32_t inst, const uint64_t *d_moves, 
                             int64_t t_star_s, uint64_t *d_key, float *d_cost_km,
                             int32_t *d_makespan_s, uint8_t *d_flags);
 
+/* bl_evaluate_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, outputs and errors, and the same kernels,
+ * but the deferred-candidate list of the one-candidate-per-lane launch and
+ * its count live in a file-scope device array of the library (4 MiB + 256 B
+ * per GPU, held until the process ends) instead of the instance's own
+ * allocation.  Calls no allocating routine.  n <= 2^24 (BL_EINVAL beyond);
+ * the array holds 2^20 deferred candidates, a launch that defers more
+ * finishes the rest in its first pass.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other contexts
+ * or threads) race and must be serialised by the caller.  BL_EDEVICE if the
+ * array's device address could not be found when the context was created.
+ * Not timed by bl_timing_enable.  Async. */
+bl_status bl_evaluate_batch_static(bl_ctx *ctx, int32_t inst, const uint64_t *d_moves, uint32_t n,
+                                   int64_t t_star_s, uint64_t *d_key, float *d_cost_km,
+                                   int32_t *d_makespan_s, uint8_t *d_flags);
+
 /* The argmin of Algorithm 1's GPU version (sec. 2.5): the minimum of n keys
  * from bl_evaluate_batch into *d_best (device), i.e. the cheapest candidate
  * that is feasible (eq. (2)) and not discarded by the makespan gate, or

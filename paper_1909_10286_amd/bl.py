@@ -96,6 +96,8 @@ _SIGS = {
                                 C.c_uint32, C.c_uint32, C.c_void_p]),
     "bl_evaluate_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint32, C.c_int64,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bl_evaluate_batch_static": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint32, C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bl_select_best": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
     "bl_search_start": (C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32]),
     "bl_search_step": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_SearchParams)]),
@@ -285,6 +287,13 @@ class Context:
     def evaluate_batch(self, inst_id, d_moves, n, t_star_s, d_key, d_cost=None, d_makespan=None,
                        d_flags=None):
         self._check(self._lib.bl_evaluate_batch(
+            self._h, inst_id, C.c_void_p(_ptr(d_moves)), n, int(t_star_s),
+            C.c_void_p(_ptr(d_key)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_makespan)),
+            C.c_void_p(_ptr(d_flags))))
+
+    def evaluate_batch_static(self, inst_id, d_moves, n, t_star_s, d_key, d_cost=None, d_makespan=None,
+                              d_flags=None):
+        self._check(self._lib.bl_evaluate_batch_static(
             self._h, inst_id, C.c_void_p(_ptr(d_moves)), n, int(t_star_s),
             C.c_void_p(_ptr(d_key)), C.c_void_p(_ptr(d_cost)), C.c_void_p(_ptr(d_makespan)),
             C.c_void_p(_ptr(d_flags))))

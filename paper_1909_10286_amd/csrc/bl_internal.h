@@ -15,6 +15,10 @@ constexpr uint32_t kMaxCand = 1u << 24;
 // Room for candidates whose long rebalancing tails an evaluation launch
 // moves to its second pass; the ones beyond it finish in the first.
 constexpr uint32_t kDeferCap = 1u << 20;
+// Deferred-list room of bl_evaluate_batch_static, whose list and count live
+// in a file-scope device array (eval.hip) instead of the instance's
+// allocation.
+constexpr uint32_t kStaticDeferCap = 1u << 20;
 
 constexpr uint64_t kInfKey = ~0ull;
 constexpr int64_t kInfT = INT64_MAX;
@@ -140,6 +144,9 @@ hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t
                           uint32_t inst_index, hipStream_t s);
 hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, uint32_t inst_index,
                            uint32_t first, uint32_t n, uint64_t *out, hipStream_t s);
+// Device address of the static array behind bl_evaluate_batch_static on the
+// current device (kStaticDeferCap + 64 words).
+hipError_t static_scratch_address(uint32_t **out);
 hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
                              uint8_t *flags, int grid, hipStream_t s);

@@ -890,6 +890,17 @@ static InstParams pass_params(const InstParams &P, uint32_t n, int grid) {
   return Q;
 }
 
+// The deferred-candidate list (kStaticDeferCap words) and its count of
+// bl_evaluate_batch_static, for callers that cannot allocate: 4 MiB + 256 B
+// that every GPU the library runs on holds until the process ends.  In host
+// code `scratch` names a host-side stand-in; its device address comes from
+// static_scratch_address, once per device.
+static __device__ __align__(256) uint32_t scratch[kStaticDeferCap + 64];
+
+hipError_t static_scratch_address(uint32_t **out) {
+  return hipGetSymbolAddress(reinterpret_cast<void **>(out), HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
                              uint8_t *flags, int grid, hipStream_t s) {

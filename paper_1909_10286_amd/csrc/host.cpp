@@ -11,6 +11,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/bl.h"
@@ -90,6 +91,7 @@ struct bl_ctx {
   int timing = 0;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
+  uint32_t *scratch = nullptr;   // device address of the static array (bl_evaluate_batch_static)
 };
 
 namespace {
@@ -420,6 +422,11 @@ bl_status capture_steps(bl_ctx *c, uint32_t n_steps, Body body, int32_t *graph) 
   return BL_OK;
 }
 
+// Device addresses of the static array behind bl_evaluate_batch_static,
+// looked up once per device (each GPU holds its own copy of the array).
+std::mutex g_scratch_mu;
+std::vector<uint32_t *> g_scratch;
+
 }  // namespace
 
 extern "C" {
@@ -451,6 +458,17 @@ bl_status bl_create(int32_t device, bl_ctx **out) {
   if (!c) return BL_ENOMEM;
   c->device = device;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch.size() < (size_t)n) g_scratch.resize((size_t)n, nullptr);
+    if (!g_scratch[device]) {
+      uint32_t *p = nullptr;
+      // On failure the entry point that needs the array reports it.
+      if (static_scratch_address(&p) == hipSuccess) g_scratch[device] = p;
+      else (void)hipGetLastError();
+    }
+    c->scratch = g_scratch[device];
+  }
   *out = c;
   return BL_OK;
 }
@@ -841,6 +859,31 @@ bl_status bl_evaluate_batch(bl_ctx *c, int32_t id, const uint64_t *d_moves, uint
   HIP_TRY(c, launch_eval_batch(I->P, d_moves, n, t_star_s, d_key, d_cost_km, d_makespan_s, d_flags,
                                grid_for(c, *I, n, false), c->stream));
   HIP_TRY(c, timing_mark(c));
+  return BL_OK;
+}
+
+bl_status bl_evaluate_batch_static(bl_ctx *c, int32_t id, const uint64_t *d_moves, uint32_t n,
+                                   int64_t t_star_s, uint64_t *d_key, float *d_cost_km,
+                                   int32_t *d_makespan_s, uint8_t *d_flags) {
+  Instance *I = get_inst(c, id);
+  if (!I) return fail(c, BL_EINVAL, "bad instance id %d", id);
+  if (!I->base_ready) return fail(c, BL_ESTATE, "no base solution uploaded");
+  if (n > kMaxCand) return fail(c, BL_EINVAL, "n %u > 2^24", n);
+  if (n && (!d_moves || !d_key)) return fail(c, BL_EINVAL, "null move or key buffer");
+  if (!c->scratch) return fail(c, BL_EDEVICE, "static scratch array unavailable on device %d", c->device);
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (n == 0) return BL_OK;
+  // The same launch, its deferred list and count in the static array (the
+  // count is cleared by a kernel at the start of the launch).  No timing
+  // events: their first use would create events.
+  InstParams Q = I->P;
+  if (Q.defer_cap) {
+    Q.defer = c->scratch;
+    Q.defer_cnt = c->scratch + kStaticDeferCap;
+    Q.defer_cap = kStaticDeferCap;
+  }
+  HIP_TRY(c, launch_eval_batch(Q, d_moves, n, t_star_s, d_key, d_cost_km, d_makespan_s, d_flags,
+                               grid_for(c, *I, n, false), c->stream));
   return BL_OK;
 }
 
