@@ -689,11 +689,14 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
 constexpr uint32_t kLocalDefer = 1024;
 
 template <int N, bool SMALL>
-__global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
+__global__ __launch_bounds__(256, kLaneWaves) void k_eval_multi_lane(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   __shared__ uint32_t s_item, s_qn;
   __shared__ uint32_t s_q[kLocalDefer];
   __shared__ LaneBase s_base;
+  __shared__ uint64_t s_qw[4][kLaneQueue];
+  __shared__ uint32_t s_qc[4][kLaneQueue];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int cur = -1;
   while (true) {
     if (threadIdx.x == 0) {
@@ -727,26 +730,62 @@ __global__ __launch_bounds__(256) void k_eval_multi_lane(BatchParams B) {
     const int nt = P.NT;
     const int su_limit = su_defer_rounds(nt);
     uint64_t best = kInfKey;
-    for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-      const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
-      if (!m.valid) continue;
-      LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, su_limit, nt);
-      if (o.deferred) {
+    // As in k_eval_lane: each wave checks 64 candidates at a time for
+    // validity and eq. (2) and evaluates the feasible ones 64 at a time from
+    // a queue in LDS.  A candidate whose SU rounds pass su_limit goes to the
+    // work item's tail queue (or, when that is full, is finished here).
+    auto evaluate = [&](uint32_t c, uint64_t w) {
+      const Move m = decode_move(w, V, P);
+      LaneOut o;
+      for (int lim = su_limit;; lim = 0) {
+        o = eval_lane<N, SMALL>(V, P, s_base, m, lim, nt);
+        if (!o.deferred) break;
         const uint32_t slot = atomicAdd(&s_qn, 1u);
         if (slot < kLocalDefer) {
           s_q[slot] = c;
-          continue;
+          return;
         }
-        o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);   // no room: finish here
       }
       if (o.feasible && !is_gated(o.makespan, t_star, P.flags)) {
         const uint64_t key = (o.cost << 24) | (uint64_t)c;
         best = key < best ? key : best;
       }
+    };
+    uint64_t *qw = s_qw[wave];
+    uint32_t *qc = s_qc[wave];
+    uint32_t qn = 0;   // wave-uniform
+    for (uint32_t i0 = c0 + (uint32_t)wave * 64u;; i0 += blockDim.x) {
+      const bool more = i0 < c1;
+      if (more) {
+        const uint32_t c = i0 + (uint32_t)lane;
+        bool feas = false;
+        uint64_t w = 0;
+        if (c < c1) {
+          w = draw_move(B.seed, c, it, idx, V, P);
+          const Move m = decode_move(w, V, P);
+          feas = m.valid && delta_feasible(V, m);
+        }
+        const uint64_t bal = __ballot(feas);
+        if (feas) {
+          const uint32_t at = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          qw[at] = w;
+          qc[at] = c;
+        }
+        qn += (uint32_t)__popcll(bal);
+      }
+      while (qn >= 64u || (!more && qn > 0u)) {
+        lane_wave_sync();
+        const uint32_t take = qn < 64u ? qn : 64u;
+        if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane]);
+        lane_wave_sync();
+        qn -= take;
+      }
+      if (!more) break;
     }
     __syncthreads();
-    const uint32_t qn = s_qn < kLocalDefer ? s_qn : kLocalDefer;
-    for (uint32_t i = threadIdx.x; i < qn; i += blockDim.x) {
+    const uint32_t qd = s_qn < kLocalDefer ? s_qn : kLocalDefer;
+    for (uint32_t i = threadIdx.x; i < qd; i += blockDim.x) {
       const uint32_t c = s_q[i];
       const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
       const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);
