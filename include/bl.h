@@ -255,6 +255,11 @@ typedef struct {
   uint32_t tile[3];
   /* 0: members in id order; 1: members with more fields first. */
   uint32_t order_policy;
+  /* One candidate per lane only (ignored otherwise).  1: each wave checks
+   * eq. (2) for 64 candidates at a time and evaluates the feasible ones 64 at
+   * a time from a queue in LDS (pays where many candidates break eq. (2));
+   * 0: each lane evaluates its candidates in turn (fewer registers). */
+  uint32_t feas_queue;
 } bl_batch_schedule;
 
 bl_status bl_batch_create(bl_ctx *ctx, const int32_t *inst_ids, int32_t n_inst, uint32_t n_cand,

@@ -73,7 +73,7 @@ class _SurStats(C.Structure):
 
 
 class _Schedule(C.Structure):
-    _fields_ = [("tile", C.c_uint32 * 3), ("order_policy", C.c_uint32)]
+    _fields_ = [("tile", C.c_uint32 * 3), ("order_policy", C.c_uint32), ("feas_queue", C.c_uint32)]
 
 
 class _TraceRow(C.Structure):
@@ -355,8 +355,8 @@ class Context:
         p = _SearchParams(seed, eps_threshold, 0, inst_index)
         self._check(self._lib.bl_batch_step(self._h, batch, C.byref(p)))
 
-    def batch_set_schedule(self, batch: int, tiles, order_policy: int):
-        s = _Schedule((C.c_uint32 * 3)(*tiles), order_policy)
+    def batch_set_schedule(self, batch: int, tiles, order_policy: int, feas_queue: int = 1):
+        s = _Schedule((C.c_uint32 * 3)(*tiles), order_policy, feas_queue)
         self._check(self._lib.bl_batch_set_schedule(self._h, batch, C.byref(s)))
 
     def batch_autotune(self, batch: int, seed: int, eps_threshold: int, cache_path=None,
@@ -365,7 +365,7 @@ class Context:
         s = _Schedule()
         path = None if cache_path is None else os.fsencode(cache_path)
         self._check(self._lib.bl_batch_autotune(self._h, batch, C.byref(p), path, C.byref(s)))
-        return dict(tile=list(s.tile), order_policy=s.order_policy)
+        return dict(tile=list(s.tile), order_policy=s.order_policy, feas_queue=s.feas_queue)
 
     # ----------------------------------------------------------- graphs --
     def search_capture(self, inst_id: int, seed: int, eps_threshold: int, n: int, n_steps: int,

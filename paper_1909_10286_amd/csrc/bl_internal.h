@@ -137,6 +137,7 @@ struct BatchParams {
   uint32_t walk;             // some member asks for the full walk (host side)
   uint32_t lane_n;           // > 0: one candidate per lane with this many tour slots (host side)
   uint32_t lane_small;       // every member has at most 32 HUs and 64 SUs (host side)
+  uint32_t feas_queue;       // lane version: per-wave queue of the candidates that pass eq. (2) (host side)
 };
 
 // Kernel entry points (launch wrappers defined in eval.hip).
@@ -165,7 +166,7 @@ size_t eval_lds_bytes(const InstParams &P);
 bool lane_eval_on(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);
-int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small);
+int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small, bool feas_queue);
 // Tour slots of the one-candidate-per-lane batched kernel for members of at
 // most max_nt tours (4, 8 or 12), 0 beyond 12.
 int batch_lane_tours(int max_nt);

@@ -688,14 +688,16 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
 // candidates are done.
 constexpr uint32_t kLocalDefer = 1024;
 
-template <int N, bool SMALL>
-__global__ __launch_bounds__(256, kLaneWaves) void k_eval_multi_lane(BatchParams B) {
+// QUEUE: the per-wave feasibility queue of k_eval_lane (the schedule's
+// feas_queue; the autotuner times both).  It pays where many candidates break
+// eq. (2) (batch256: 3.63 to 3.40 ms per iteration) and costs registers where
+// few do (the paper-scale replica: 0.254 to 0.289 ms).
+template <int N, bool SMALL, bool QUEUE>
+__global__ __launch_bounds__(256, QUEUE ? kLaneWaves : 1) void k_eval_multi_lane(BatchParams B) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   __shared__ uint32_t s_item, s_qn;
   __shared__ uint32_t s_q[kLocalDefer];
   __shared__ LaneBase s_base;
-  __shared__ uint64_t s_qw[4][kLaneQueue];
-  __shared__ uint32_t s_qc[4][kLaneQueue];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int cur = -1;
   while (true) {
@@ -730,10 +732,11 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_multi_lane(BatchParams
     const int nt = P.NT;
     const int su_limit = su_defer_rounds(nt);
     uint64_t best = kInfKey;
-    // As in k_eval_lane: each wave checks 64 candidates at a time for
-    // validity and eq. (2) and evaluates the feasible ones 64 at a time from
-    // a queue in LDS.  A candidate whose SU rounds pass su_limit goes to the
-    // work item's tail queue (or, when that is full, is finished here).
+    // A candidate whose SU rounds pass su_limit goes to the work item's tail
+    // queue (or, when that is full, is finished here).  Without QUEUE each
+    // lane takes the item's candidates in turn; with it, as in k_eval_lane,
+    // each wave checks 64 candidates at a time for validity and eq. (2) and
+    // evaluates the feasible ones 64 at a time from a queue in LDS.
     auto evaluate = [&](uint32_t c, uint64_t w) {
       const Move m = decode_move(w, V, P);
       LaneOut o;
@@ -751,37 +754,46 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_multi_lane(BatchParams
         best = key < best ? key : best;
       }
     };
-    uint64_t *qw = s_qw[wave];
-    uint32_t *qc = s_qc[wave];
-    uint32_t qn = 0;   // wave-uniform
-    for (uint32_t i0 = c0 + (uint32_t)wave * 64u;; i0 += blockDim.x) {
-      const bool more = i0 < c1;
-      if (more) {
-        const uint32_t c = i0 + (uint32_t)lane;
-        bool feas = false;
-        uint64_t w = 0;
-        if (c < c1) {
-          w = draw_move(B.seed, c, it, idx, V, P);
-          const Move m = decode_move(w, V, P);
-          feas = m.valid && delta_feasible(V, m);
-        }
-        const uint64_t bal = __ballot(feas);
-        if (feas) {
-          const uint32_t at = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          qw[at] = w;
-          qc[at] = c;
-        }
-        qn += (uint32_t)__popcll(bal);
+    if constexpr (!QUEUE) {
+      for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const uint64_t w = draw_move(B.seed, c, it, idx, V, P);
+        if (decode_move(w, V, P).valid) evaluate(c, w);
       }
-      while (qn >= 64u || (!more && qn > 0u)) {
-        lane_wave_sync();
-        const uint32_t take = qn < 64u ? qn : 64u;
-        if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane]);
-        lane_wave_sync();
-        qn -= take;
+    } else {
+      __shared__ uint64_t s_qw[4][kLaneQueue];
+      __shared__ uint32_t s_qc[4][kLaneQueue];
+      uint64_t *qw = s_qw[wave];
+      uint32_t *qc = s_qc[wave];
+      uint32_t qn = 0;   // wave-uniform
+      for (uint32_t i0 = c0 + (uint32_t)wave * 64u;; i0 += blockDim.x) {
+        const bool more = i0 < c1;
+        if (more) {
+          const uint32_t c = i0 + (uint32_t)lane;
+          bool feas = false;
+          uint64_t w = 0;
+          if (c < c1) {
+            w = draw_move(B.seed, c, it, idx, V, P);
+            const Move m = decode_move(w, V, P);
+            feas = m.valid && delta_feasible(V, m);
+          }
+          const uint64_t bal = __ballot(feas);
+          if (feas) {
+            const uint32_t at = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            qw[at] = w;
+            qc[at] = c;
+          }
+          qn += (uint32_t)__popcll(bal);
+        }
+        while (qn >= 64u || (!more && qn > 0u)) {
+          lane_wave_sync();
+          const uint32_t take = qn < 64u ? qn : 64u;
+          if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane]);
+          lane_wave_sync();
+          qn -= take;
+        }
+        if (!more) break;
       }
-      if (!more) break;
     }
     __syncthreads();
     const uint32_t qd = s_qn < kLocalDefer ? s_qn : kLocalDefer;
@@ -1031,17 +1043,18 @@ int eval_occupancy(const InstParams &P, bool search) {
 size_t batch_lds_bytes(uint32_t max_image_words) { return (size_t)round4(max_image_words) * 4; }
 
 template <int N, bool SMALL>
-int multi_lane_occupancy(size_t lds) {
+int multi_lane_occupancy(size_t lds, bool queue) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi_lane<N, SMALL>, 256, lds);
+  const hipError_t e = queue ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi_lane<N, SMALL, true>, 256, lds)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_multi_lane<N, SMALL, false>, 256, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small) {
+int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small, bool queue) {
   switch (lane_n) {
-    case 4: return lane_small ? multi_lane_occupancy<4, true>(lds) : multi_lane_occupancy<4, false>(lds);
-    case 8: return lane_small ? multi_lane_occupancy<8, true>(lds) : multi_lane_occupancy<8, false>(lds);
-    case 12: return lane_small ? multi_lane_occupancy<12, true>(lds) : multi_lane_occupancy<12, false>(lds);
+    case 4: return lane_small ? multi_lane_occupancy<4, true>(lds, queue) : multi_lane_occupancy<4, false>(lds, queue);
+    case 8: return lane_small ? multi_lane_occupancy<8, true>(lds, queue) : multi_lane_occupancy<8, false>(lds, queue);
+    case 12: return lane_small ? multi_lane_occupancy<12, true>(lds, queue) : multi_lane_occupancy<12, false>(lds, queue);
     default: break;
   }
   int nb = 0;
@@ -1063,8 +1076,13 @@ hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStre
   switch (B.lane_n) {
 #define BL_MULTI_LANE(N) \
     case N: \
-      if (B.lane_small) hipLaunchKernelGGL((k_eval_multi_lane<N, true>), dim3(grid), dim3(256), lds, s, B); \
-      else hipLaunchKernelGGL((k_eval_multi_lane<N, false>), dim3(grid), dim3(256), lds, s, B); \
+      if (B.feas_queue) { \
+        if (B.lane_small) hipLaunchKernelGGL((k_eval_multi_lane<N, true, true>), dim3(grid), dim3(256), lds, s, B); \
+        else hipLaunchKernelGGL((k_eval_multi_lane<N, false, true>), dim3(grid), dim3(256), lds, s, B); \
+      } else { \
+        if (B.lane_small) hipLaunchKernelGGL((k_eval_multi_lane<N, true, false>), dim3(grid), dim3(256), lds, s, B); \
+        else hipLaunchKernelGGL((k_eval_multi_lane<N, false, false>), dim3(grid), dim3(256), lds, s, B); \
+      } \
       return hipGetLastError();
     BL_MULTI_LANE(4) BL_MULTI_LANE(8) BL_MULTI_LANE(12)
 #undef BL_MULTI_LANE

@@ -61,13 +61,13 @@ struct Sur {
 struct Batch {
   std::vector<int32_t> members;
   uint32_t n = 0;
-  bl_batch_schedule sched{{1024, 1024, 1024}, 1};
+  bl_batch_schedule sched{{1024, 1024, 1024}, 1, 1};
   InstParams *d_inst = nullptr;  // [K]
   uint32_t *d_sched = nullptr;   // item_off[K+1] | order[K] | tile[K] | queue[1]
   uint32_t total_items = 0;
   uint32_t max_image_words = 0;
   size_t lds = 0;
-  int occ = 1;
+  int occ[2] = {1, 1};   // workgroups per CU without and with the feasibility queue
   bool walk = false;  // some member asks for the full walk
   int lane_n = 0;     // > 0: one candidate per lane, this many tour slots
   bool lane_small = false;
@@ -273,6 +273,7 @@ bl_status apply_schedule(bl_ctx *c, Batch &B, const bl_batch_schedule &s) {
       return fail(c, BL_EINVAL, "tile[%d] = %u must be a power of two in 64..65536", k, t);
   }
   if (s.order_policy > 1) return fail(c, BL_EINVAL, "order_policy must be 0 or 1");
+  if (s.feas_queue > 1) return fail(c, BL_EINVAL, "feas_queue must be 0 or 1");
   const uint32_t K = (uint32_t)B.members.size();
   std::vector<uint32_t> order(K);
   std::iota(order.begin(), order.end(), 0u);
@@ -311,11 +312,13 @@ BatchParams batch_params(const Batch &B, const bl_search_params *p) {
   bp.walk = B.walk ? 1u : 0u;
   bp.lane_n = (uint32_t)B.lane_n;
   bp.lane_small = B.lane_small ? 1u : 0u;
+  bp.feas_queue = B.sched.feas_queue;
   return bp;
 }
 
 int batch_grid(const bl_ctx *c, const Batch &B) {
-  return (int)std::max<uint32_t>(1u, std::min<uint32_t>(B.total_items, (uint32_t)(c->n_cu * B.occ)));
+  const int occ = B.occ[B.sched.feas_queue ? 1 : 0];
+  return (int)std::max<uint32_t>(1u, std::min<uint32_t>(B.total_items, (uint32_t)(c->n_cu * occ)));
 }
 
 bl_status batch_step_on(bl_ctx *c, Batch &B, const bl_search_params *p, hipStream_t q) {
@@ -366,14 +369,15 @@ bool read_file(const char *path, std::string &out) {
 bool cache_lookup(const std::string &text, const std::string &sig, bl_batch_schedule &s) {
   const size_t at = text.find("\"" + sig + "\"");
   if (at == std::string::npos) return false;
-  unsigned a, b, d, pol;
-  if (sscanf(text.c_str() + at + sig.size() + 2, " : {\"tile\": [%u, %u, %u], \"order_policy\": %u",
-             &a, &b, &d, &pol) != 4)
+  unsigned a, b, d, pol, fq;
+  if (sscanf(text.c_str() + at + sig.size() + 2,
+             " : {\"tile\": [%u, %u, %u], \"order_policy\": %u, \"feas_queue\": %u", &a, &b, &d, &pol, &fq) != 5)
     return false;
   s.tile[0] = a;
   s.tile[1] = b;
   s.tile[2] = d;
   s.order_policy = pol;
+  s.feas_queue = fq;
   return true;
 }
 
@@ -381,8 +385,8 @@ bool cache_store(const char *path, std::string text, const std::string &sig,
                  const bl_batch_schedule &s, double ms) {
   char entry[256];
   snprintf(entry, sizeof entry,
-           "  \"%s\": {\"tile\": [%u, %u, %u], \"order_policy\": %u, \"eval_ms\": %.4f}", sig.c_str(),
-           s.tile[0], s.tile[1], s.tile[2], s.order_policy, ms);
+           "  \"%s\": {\"tile\": [%u, %u, %u], \"order_policy\": %u, \"feas_queue\": %u, \"eval_ms\": %.4f}",
+           sig.c_str(), s.tile[0], s.tile[1], s.tile[2], s.order_policy, s.feas_queue, ms);
   const size_t close = text.rfind('}');
   if (text.find('"') == std::string::npos || close == std::string::npos)
     text = std::string("{\n") + entry + "\n}\n";
@@ -986,7 +990,7 @@ bl_status bl_batch_create(bl_ctx *c, const int32_t *ids, int32_t n_inst, uint32_
   B->lds = batch_lds_bytes(B->max_image_words);
   if (B->lds > 160 * 1024) return fail(c, BL_EINVAL, "member image exceeds LDS");
   HIP_TRY(c, hipSetDevice(c->device));
-  B->occ = batch_occupancy(B->lds, B->walk, B->lane_n, B->lane_small);
+  for (int q = 0; q < 2; ++q) B->occ[q] = batch_occupancy(B->lds, B->walk, B->lane_n, B->lane_small, q == 1);
   const size_t K = B->members.size();
   HIP_TRY(c, hipMalloc(&B->d_inst, K * sizeof(InstParams)));
   if (hipMalloc(&B->d_sched, (3 * K + 2) * sizeof(uint32_t)) != hipSuccess) {
@@ -1083,10 +1087,11 @@ bl_status bl_batch_autotune(bl_ctx *c, int32_t id, const bl_search_params *p, co
   bool present[3] = {false, false, false};
   for (int32_t m : B->members) present[size_class(c->inst[m]->NF)] = true;
   const uint32_t tiles[] = {256, 512, 1024, 2048, 4096};
-  best = bl_batch_schedule{{1024, 1024, 1024}, 1};
+  best = bl_batch_schedule{{1024, 1024, 1024}, 1, 1};
   double best_ms = 0;
   bl_status st = time_sched(best, best_ms);
-  // Coordinate descent: one size class at a time, then the member order.
+  // Coordinate descent: one size class at a time, then the member order,
+  // then the feasibility queue.
   for (int k = 0; k < 3 && st == BL_OK; ++k) {
     if (!present[k]) continue;
     for (uint32_t t : tiles) {
@@ -1100,6 +1105,13 @@ bl_status bl_batch_autotune(bl_ctx *c, int32_t id, const bl_search_params *p, co
   if (st == BL_OK) {
     bl_batch_schedule s = best;
     s.order_policy = 1 - s.order_policy;
+    double ms = 0;
+    st = time_sched(s, ms);
+    if (st == BL_OK && ms < best_ms) best_ms = ms, best = s;
+  }
+  if (st == BL_OK && B->lane_n > 0) {
+    bl_batch_schedule s = best;
+    s.feas_queue = 1 - s.feas_queue;
     double ms = 0;
     st = time_sched(s, ms);
     if (st == BL_OK && ms < best_ms) best_ms = ms, best = s;

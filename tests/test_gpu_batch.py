@@ -96,12 +96,13 @@ def test_batch_schedule_and_graph_do_not_change_results(ctx, tmp_path):
     ks = [0, 5, 77, 120, 201, 255]
     base = _batch_traces(ctx, ks, 4096, 6)
     assert _batch_traces(ctx, ks, 4096, 6, sched=([64, 128, 65536], 0)) == base
+    assert _batch_traces(ctx, ks, 4096, 6, sched=([256, 1024, 512], 1, 0)) == base   # no feasibility queue
     assert _batch_traces(ctx, ks, 4096, 6, graph_steps=2) == base
     cache = tmp_path / "sched.json"
     info = {"path": str(cache)}
     assert _batch_traces(ctx, ks, 4096, 6, autotune=info) == base
     first = info["result"]
-    assert all(t in (256, 512, 1024, 2048, 4096) for t in first["tile"])
+    assert all(t in (256, 512, 1024, 2048, 4096) for t in first["tile"]) and first["feas_queue"] in (0, 1)
     data = json.loads(cache.read_text())
     assert len(data) == 1
     again = {"path": str(cache)}
