@@ -117,6 +117,7 @@ struct InstParams {
   uint32_t *defer;     // [defer_cap] candidates whose SU rounds an evaluation launch left for its second pass
   uint32_t *defer_cnt; // their count
   uint32_t defer_cap;  // 0: no deferral
+  uint32_t defer_zeroed; // host side: the base preparation of this iteration already cleared the count
   uint16_t *hu_id;     // rank -> HU id
   uint16_t *su_id;     // rank -> SU id
 };
@@ -151,9 +152,12 @@ hipError_t static_scratch_address(uint32_t **out);
 hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,
                              uint8_t *flags, int grid, hipStream_t s);
+// count_zeroed: the search-mode base preparation just before this launch
+// cleared the deferred count (it does), so the launch skips its own clearing
+// kernel.
 hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
                               uint32_t inst_index, int grid, hipStream_t s,
-                              const uint32_t *run_flag = nullptr);
+                              const uint32_t *run_flag = nullptr, bool count_zeroed = false);
 hipError_t launch_eval_gather(const InstParams &P, uint64_t seed, const uint32_t *idx, uint32_t n,
                               uint32_t inst_index, uint64_t *key, float *cost, int grid,
                               hipStream_t s);

@@ -333,6 +333,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
       t_end[g] = (uint16_t)run;
     }
     *P.best_key = kInfKey;
+    if (mode == kPrepSearch && P.defer_cap) *P.defer_cnt = 0u;   // the evaluation launch's deferred count
   }
   __syncthreads();
   const uint32_t nb1 = 1u + (uint32_t)P.NB;
@@ -905,7 +906,7 @@ hipError_t launch_lane_phase(const InstParams &P, int phase, int grid, hipStream
 // (by a kernel, so that the sequence can be captured in a graph).
 template <int MODE, bool SMALL, class... A>
 hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
-  if (P.defer_cap) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, P.defer_cnt, 0u);
+  if (P.defer_cap && !P.defer_zeroed) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, P.defer_cnt, 0u);
   hipError_t e = launch_lane_phase<MODE, SMALL>(P, 0, grid, s, a...);
   if (e != hipSuccess || !P.defer_cap) return e;
   return launch_lane_phase<MODE, SMALL>(P, 1, grid, s, a...);
@@ -962,9 +963,11 @@ hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_
 
 hipError_t launch_eval_search(const InstParams &P, uint64_t seed, uint32_t n,
                               uint32_t inst_index, int grid, hipStream_t s,
-                              const uint32_t *run_flag) {
+                              const uint32_t *run_flag, bool count_zeroed) {
   if (n == 0) return hipSuccess;
-  return launch_k_eval<kModeSearch>(pass_params(P, n, grid), grid, s, (const uint64_t *)nullptr, n, (int64_t)0, seed,
+  InstParams Q = pass_params(P, n, grid);
+  Q.defer_zeroed = count_zeroed ? 1u : 0u;
+  return launch_k_eval<kModeSearch>(Q, grid, s, (const uint64_t *)nullptr, n, (int64_t)0, seed,
                                     inst_index, (uint64_t *)nullptr, (float *)nullptr,
                                     (int32_t *)nullptr, (uint8_t *)nullptr, (const uint32_t *)nullptr,
                                     run_flag);

@@ -244,7 +244,8 @@ int grid_for(const bl_ctx *c, const Instance &I, uint32_t n, bool search) {
 bl_status search_step_on(bl_ctx *c, Instance *I, const bl_search_params *p, hipStream_t q) {
   HIP_TRY(c, launch_prepare(I->P, kPrepSearch, p->seed, p->eps_threshold, p->inst_index, q));
   HIP_TRY(c, timing_mark(c));
-  HIP_TRY(c, launch_eval_search(I->P, p->seed, p->n, p->inst_index, grid_for(c, *I, p->n, true), q));
+  HIP_TRY(c, launch_eval_search(I->P, p->seed, p->n, p->inst_index, grid_for(c, *I, p->n, true), q, nullptr,
+                                true));
   HIP_TRY(c, timing_mark(c));
   HIP_TRY(c, launch_commit(I->P, kCommitStep, p->seed, p->inst_index, q));
   return BL_OK;
@@ -707,6 +708,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   P.su_id = R->d_units + NHU;
   if (eval_lds_bytes(P) > 160 * 1024) return cleanup(fail(c, BL_EINVAL, "instance image exceeds LDS"));
   P.defer = nullptr;
+  P.defer_zeroed = 0;
   P.defer_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(R->d_best) + 8);
   P.defer_cap = 0;
   if (lane_eval_on(P)) {
