@@ -201,11 +201,11 @@ bl_status bl_evaluate_batch(bl_ctx *ctx, int32_t inst, const uint64_t *d_moves, 
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same arguments, outputs and errors, and the same kernels,
  * but the deferred-candidate list of the one-candidate-per-lane launch and
- * its count live in a file-scope device array of the library (4 MiB + 256 B
+ * its counts live in a file-scope device array of the library (8 MiB + 256 B
  * per GPU, held until the process ends) instead of the instance's own
  * allocation.  Calls no allocating routine.  n <= 2^24 (BL_EINVAL beyond);
- * the array holds 2^20 deferred candidates, a launch that defers more
- * finishes the rest in its first pass.  Every call on one GPU shares that
+ * the array holds 2^20 deferred BP moves and 2^20 deferred field moves, a
+ * launch that defers more finishes the rest in its first pass.  Every call on one GPU shares that
  * GPU's array: calls that overlap on one GPU (other streams, other contexts
  * or threads) race and must be serialised by the caller.  BL_EDEVICE if the
  * array's device address could not be found when the context was created.

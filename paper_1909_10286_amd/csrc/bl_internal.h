@@ -114,9 +114,10 @@ struct InstParams {
   TraceRow *trace;
   uint32_t trace_cap;
   uint64_t *best_key;  // per-instance argmin slot
-  uint32_t *defer;     // [defer_cap] candidates whose SU rounds an evaluation launch left for its second pass
-  uint32_t *defer_cnt; // their count
-  uint32_t defer_cap;  // 0: no deferral
+  uint32_t *defer;     // [2 defer_cap] candidates whose SU rounds an evaluation launch left for its
+                       // second pass: BP moves in the first defer_cap entries, field moves after them
+  uint32_t *defer_cnt; // [2] their counts per class
+  uint32_t defer_cap;  // entries per class; 0: no deferral
   uint32_t defer_zeroed; // host side: the base preparation of this iteration already cleared the count
   uint16_t *hu_id;     // rank -> HU id
   uint16_t *su_id;     // rank -> SU id
@@ -147,7 +148,7 @@ hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t
 hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, uint32_t inst_index,
                            uint32_t first, uint32_t n, uint64_t *out, hipStream_t s);
 // Device address of the static array behind bl_evaluate_batch_static on the
-// current device (kStaticDeferCap + 64 words).
+// current device (2 kStaticDeferCap + 64 words).
 hipError_t static_scratch_address(uint32_t **out);
 hipError_t launch_eval_batch(const InstParams &P, const uint64_t *moves, uint32_t n,
                              int64_t t_star, uint64_t *key, float *cost, int32_t *mk,

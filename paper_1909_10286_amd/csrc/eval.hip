@@ -94,23 +94,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 // 10 tours.
 constexpr int su_defer_rounds(int n_tours) { return n_tours <= 6 ? 3 : 1; }
 
-// Slot in the deferred list for a lane whose candidate is deferred (the
-// value means nothing for the others).  WAVE: one atomic per wave for its
-// deferring lanes, each taking the slot of its rank among them (every active
-// lane calls it); it pays where many lanes defer (a one-round limit: 3.4 %
-// faster at 10 tours, 1.5 % slower at 5 with three rounds).  Else one
-// atomic per deferring lane.
-template <bool WAVE>
-__device__ __forceinline__ uint32_t defer_slot(bool deferred, uint32_t *cnt) {
-  if (!WAVE) return deferred ? atomicAdd(cnt, 1u) : 0u;
-  const uint64_t dmask = __ballot(deferred);
-  if (!dmask) return 0u;
-  const int leader = __ffsll((unsigned long long)dmask) - 1;
-  uint32_t base = 0;
-  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(cnt, (uint32_t)__popcll(dmask));
-  base = __shfl(base, leader);
-  return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(dmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dmask, 0u));
-}
+// The deferred list holds two classes, each in a part of its own with a
+// count of its own: BP moves (class 0) and field moves (class 1).  A BP move
+// carries a whole BP's fields and changes its tours' mean distances more, so
+// its SU tails run longer (clust500 after 200 iterations: 20 rounds on
+// average, up to 66, against 10, up to 19, for field moves); the second pass
+// takes the BP moves first, in waves of their own, and the field moves after
+// them.  A workgroup collects its deferred candidates in LDS and appends them
+// to the list at its end with one atomic per class: with one global atomic
+// per deferring lane or wave the shared counters were the bottleneck of the
+// first pass.
+constexpr int kWgDefer = 512;   // per class and workgroup
 
 // Orders LDS traffic between the lanes of one wave.
 __device__ __forceinline__ void lane_wave_sync() {
@@ -151,11 +145,18 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
   if (run_flag && *run_flag == 0u) return;
   // The counter goes on counting past the list's room (those candidates
   // finish in the first pass), so the second pass takes at most defer_cap.
-  const uint32_t total = phase == 0 ? n : min(*P.defer_cnt, P.defer_cap);
+  // The list holds defer_cap entries per class: BP moves first, then field
+  // moves.
+  const uint32_t cap = P.defer_cap;
+  const uint32_t n_bp = phase == 0 ? 0u : min(P.defer_cnt[0], cap);
+  const uint32_t total = phase == 0 ? n : n_bp + min(P.defer_cnt[1], cap);
   if (phase == 1 && blockIdx.x * blockDim.x >= total) return;
   __shared__ LaneBase s_base;
   __shared__ uint64_t s_qw[4][kLaneQueue];
   __shared__ uint32_t s_qc[4][kLaneQueue];
+  __shared__ uint32_t s_dq[2][kWgDefer];
+  __shared__ uint32_t s_dqn[2], s_dbase[2];
+  if (threadIdx.x < 2) s_dqn[threadIdx.x] = 0u;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   stage(lds, P.image, P.lay.total_words);
   __syncthreads();
@@ -172,21 +173,28 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
   }
   const int su_limit = phase == 0 && P.defer_cap ? su_defer_rounds(N) : 0;
   uint64_t best = kInfKey;
-  // Full evaluation of feasible candidate c (move word w).  A candidate
-  // whose SU rounds pass su_limit goes to the deferred list; when the list
-  // is full it is evaluated again here with no limit (one copy of the
-  // evaluation in the code, run once or twice).
-  auto evaluate = [&](uint32_t c, uint64_t w) {
+  // Full evaluation of feasible candidate c (move word w), from round limit
+  // lim0.  A candidate whose SU rounds pass the limit goes to the
+  // workgroup's buffer (or, when that is full, straight to the list); when
+  // the list is full too it is evaluated again here with no limit (one copy
+  // of the evaluation in the code, run once or twice).
+  auto evaluate = [&](uint32_t c, uint64_t w, int lim0) {
     const uint32_t ci = MODE == kModeGather ? gather[c] : c;
     const Move m = decode_move(w, V, P);
     CandResult r{kInfKey, __builtin_inff(), 0x7FFFFFFF, 0u};
     LaneOut o;
-    for (int lim = su_limit;; lim = 0) {
+    for (int lim = lim0;; lim = 0) {
       o = eval_lane<N, SMALL>(V, P, s_base, m, lim);
-      const uint32_t slot = defer_slot<su_defer_rounds(N) == 1>(o.deferred, P.defer_cnt);
       if (!o.deferred) break;
-      if (slot < P.defer_cap) {
-        P.defer[slot] = c;
+      const int cls = m.kind == 0 ? 1 : 0;
+      const uint32_t ls = atomicAdd(&s_dqn[cls], 1u);
+      if (ls < (uint32_t)kWgDefer) {
+        s_dq[cls][ls] = c;
+        return;
+      }
+      const uint32_t slot = atomicAdd(P.defer_cnt + cls, 1u);
+      if (slot < cap) {
+        P.defer[cls * cap + slot] = c;
         return;
       }
     }
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
       uint64_t w = 0;
       uint32_t c = 0;
       if (i < total) {
-        c = phase == 0 ? i : P.defer[i];
+        c = phase == 0 ? i : P.defer[i < n_bp ? i : cap + (i - n_bp)];
         const uint32_t ci = MODE == kModeGather ? gather[c] : c;
         w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
         const Move m = decode_move(w, V, P);
@@ -246,11 +254,34 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
     while (qn >= 64u || (!more && qn > 0u)) {
       lane_wave_sync();
       const uint32_t take = qn < 64u ? qn : 64u;
-      if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane]);
+      if ((uint32_t)lane < take) evaluate(qc[qn - take + lane], qw[qn - take + lane], su_limit);
       lane_wave_sync();
       qn -= take;
     }
     if (!more) break;
+  }
+  if (su_limit) {
+    // The workgroup's deferred candidates join the list; any the list has
+    // no room for are finished here.
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      const uint32_t k = min(s_dqn[threadIdx.x], (uint32_t)kWgDefer);
+      s_dbase[threadIdx.x] = k ? atomicAdd(P.defer_cnt + threadIdx.x, k) : 0u;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int cls = 0; cls < 2; ++cls) {
+      const uint32_t k = min(s_dqn[cls], (uint32_t)kWgDefer), base = s_dbase[cls];
+      for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
+        const uint32_t c = s_dq[cls][i];
+        if (base + i < cap) {
+          P.defer[cls * cap + base + i] = c;
+        } else {
+          const uint32_t ci = MODE == kModeGather ? gather[c] : c;
+          evaluate(c, MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P), 0);
+        }
+      }
+    }
   }
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
@@ -333,7 +364,10 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
       t_end[g] = (uint16_t)run;
     }
     *P.best_key = kInfKey;
-    if (mode == kPrepSearch && P.defer_cap) *P.defer_cnt = 0u;   // the evaluation launch's deferred count
+    if (mode == kPrepSearch && P.defer_cap) {   // the evaluation launch's deferred counts
+      P.defer_cnt[0] = 0u;
+      P.defer_cnt[1] = 0u;
+    }
   }
   __syncthreads();
   const uint32_t nb1 = 1u + (uint32_t)P.NB;
@@ -742,7 +776,7 @@ __global__ __launch_bounds__(256, QUEUE ? kLaneWaves : 1) void k_eval_multi_lane
       const Move m = decode_move(w, V, P);
       LaneOut o;
       for (int lim = su_limit;; lim = 0) {
-        o = eval_lane<N, SMALL>(V, P, s_base, m, lim, nt);
+        o = eval_lane<N, SMALL>(V, P, s_base, m, lim);
         if (!o.deferred) break;
         const uint32_t slot = atomicAdd(&s_qn, 1u);
         if (slot < kLocalDefer) {
@@ -801,7 +835,7 @@ __global__ __launch_bounds__(256, QUEUE ? kLaneWaves : 1) void k_eval_multi_lane
     for (uint32_t i = threadIdx.x; i < qd; i += blockDim.x) {
       const uint32_t c = s_q[i];
       const Move m = decode_move(draw_move(B.seed, c, it, idx, V, P), V, P);
-      const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, 0, nt);
+      const LaneOut o = eval_lane<N, SMALL>(V, P, s_base, m, 0);
       if (o.feasible && !is_gated(o.makespan, t_star, P.flags)) {
         const uint64_t key = (o.cost << 24) | (uint64_t)c;
         best = key < best ? key : best;
@@ -906,7 +940,8 @@ hipError_t launch_lane_phase(const InstParams &P, int phase, int grid, hipStream
 // (by a kernel, so that the sequence can be captured in a graph).
 template <int MODE, bool SMALL, class... A>
 hipError_t launch_lane(const InstParams &P, int grid, hipStream_t s, A... a) {
-  if (P.defer_cap && !P.defer_zeroed) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, P.defer_cnt, 0u);
+  if (P.defer_cap && !P.defer_zeroed)
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, reinterpret_cast<uint64_t *>(P.defer_cnt), 0ull);
   hipError_t e = launch_lane_phase<MODE, SMALL>(P, 0, grid, s, a...);
   if (e != hipSuccess || !P.defer_cap) return e;
   return launch_lane_phase<MODE, SMALL>(P, 1, grid, s, a...);
@@ -942,12 +977,13 @@ static InstParams pass_params(const InstParams &P, uint32_t n, int grid) {
   return Q;
 }
 
-// The deferred-candidate list (kStaticDeferCap words) and its count of
-// bl_evaluate_batch_static, for callers that cannot allocate: 4 MiB + 256 B
-// that every GPU the library runs on holds until the process ends.  In host
+// The deferred-candidate list (kStaticDeferCap words per class, two
+// classes) and its counts of bl_evaluate_batch_static, for callers that
+// cannot allocate: 8 MiB + 256 B that every GPU the library runs on holds
+// until the process ends.  In host
 // code `scratch` names a host-side stand-in; its device address comes from
 // static_scratch_address, once per device.
-static __device__ __align__(256) uint32_t scratch[kStaticDeferCap + 64];
+static __device__ __align__(256) uint32_t scratch[2 * kStaticDeferCap + 64];
 
 hipError_t static_scratch_address(uint32_t **out) {
   return hipGetSymbolAddress(reinterpret_cast<void **>(out), HIP_SYMBOL(scratch));

@@ -40,8 +40,8 @@ struct Instance {
   uint16_t *d_sol = nullptr, *d_units = nullptr;
   SearchState *d_st = nullptr;
   TraceRow *d_trace = nullptr;
-  uint64_t *d_best = nullptr;   // argmin slot (8 B), then the deferred-candidate count (4 B)
-  uint32_t *d_defer = nullptr;  // deferred-candidate list of the one-candidate-per-lane launches
+  uint64_t *d_best = nullptr;   // argmin slot (8 B), then the deferred-candidate counts (2 x 4 B)
+  uint32_t *d_defer = nullptr;  // deferred-candidate list of the one-candidate-per-lane launches (2 classes)
   bool base_ready = false, started = false;
   int occ_batch = 1, occ_search = 1;
 };
@@ -712,7 +712,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   P.defer_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(R->d_best) + 8);
   P.defer_cap = 0;
   if (lane_eval_on(P)) {
-    if ((e = hipMalloc(&R->d_defer, (size_t)kDeferCap * 4)) != hipSuccess)
+    if ((e = hipMalloc(&R->d_defer, (size_t)kDeferCap * 8)) != hipSuccess)
       return cleanup(hip_fail(c, e, "hipMalloc deferred list"));
     P.defer = R->d_defer;
     P.defer_cap = kDeferCap;
@@ -879,13 +879,13 @@ bl_status bl_evaluate_batch_static(bl_ctx *c, int32_t id, const uint64_t *d_move
   if (!c->scratch) return fail(c, BL_EDEVICE, "static scratch array unavailable on device %d", c->device);
   HIP_TRY(c, hipSetDevice(c->device));
   if (n == 0) return BL_OK;
-  // The same launch, its deferred list and count in the static array (the
-  // count is cleared by a kernel at the start of the launch).  No timing
+  // The same launch, its deferred list and counts in the static array (the
+  // counts are cleared by a kernel at the start of the launch).  No timing
   // events: their first use would create events.
   InstParams Q = I->P;
   if (Q.defer_cap) {
     Q.defer = c->scratch;
-    Q.defer_cnt = c->scratch + kStaticDeferCap;
+    Q.defer_cnt = c->scratch + 2 * kStaticDeferCap;
     Q.defer_cap = kStaticDeferCap;
   }
   HIP_TRY(c, launch_eval_batch(Q, d_moves, n, t_star_s, d_key, d_cost_km, d_makespan_s, d_flags,

@@ -31,6 +31,14 @@ constexpr tm_t kTInf = INT32_MAX, kTNegInf = INT32_MIN;
 // candidate starts from these values, and its waiting time stays the
 // base's unless the HU rebalancing moves one of its HUs.
 struct LaneBase {
+  // The base's tour aggregates and unit masks, copied from the image so that
+  // the evaluation addresses them at fixed offsets (a few scalar registers
+  // fewer than the image's arrays need).  Zero beyond the instance's tours.
+  uint64_t sh[kLaneMaxTours];     // shuttle distance
+  uint64_t hu_mask[kLaneMaxTours];
+  uint64_t su_lo[kLaneMaxTours], su_hi[kLaneMaxTours];
+  uint32_t len[kLaneMaxTours], area[kLaneMaxTours], msum[kLaneMaxTours], mcnt[kLaneMaxTours];
+  int32_t nf[kLaneMaxTours];      // fields
   uint32_t R[kLaneMaxTours];
   uint32_t load[kLaneMaxTours];
   int32_t top[kLaneMaxTours];  // critical SU (largest fill time) of the base, -1 without SUs
@@ -69,6 +77,16 @@ __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const
                                   : (tm_t)udiv(7200ull * dm, V.su_speed[top]) - (tm_t)udiv(ld - V.su_fill[top], nhu);
       }
     }
+    const bool live = t < nt;
+    B.sh[t] = live ? V.t_sh[t] : 0ull;
+    B.hu_mask[t] = live ? V.hu_mask[t] : 0ull;
+    B.su_lo[t] = live ? V.su_mask[2 * t] : 0ull;
+    B.su_hi[t] = live ? V.su_mask[2 * t + 1] : 0ull;
+    B.len[t] = live ? V.t_len[t] : 0u;
+    B.area[t] = live ? V.t_area[t] : 0u;
+    B.msum[t] = live ? V.t_msum[t] : 0u;
+    B.mcnt[t] = live ? V.t_mcnt[t] : 0u;
+    B.nf[t] = live ? (int)V.t_end[t] - (int)V.t_start[t] : 0;
     B.R[t] = R;
     B.load[t] = ld;
     B.top[t] = top;
@@ -248,12 +266,13 @@ __device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned l
 // evaluation stops with `deferred` set and no result; the caller evaluates
 // the candidate again later with su_limit = 0 (no limit).
 //
-// nt: the instance's tour count, at most N.  Tours nt..N-1 are taken as
-// empty and inactive and as holding no units: they are then never g_max, g2
-// or a donor, add nothing to the cost, and the result is that of N = nt.
+// Tours from the instance's tour count up to N come from `B` as empty and
+// inactive and as holding no units (lane_base_fill): they are then never
+// g_max, g2 or a donor, add nothing to the cost, and the result is that of
+// N = the tour count.
 template <int N, bool SMALL>
 __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
-                                             const Move &m, int su_limit, int nt = N) {
+                                             const Move &m, int su_limit) {
   using HM = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
   LaneOut o;
   o.flags = 0;
@@ -274,11 +293,10 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   uint64_t shsum = 0;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    const bool live = t < nt;
-    int64_t Lx = live ? V.t_len[t] : 0u;
-    uint32_t a = live ? V.t_area[t] : 0u, ms = live ? V.t_msum[t] : 0u, mc = live ? V.t_mcnt[t] : 0u;
-    uint64_t sh = live ? V.t_sh[t] : 0ull;
-    int nf = live ? (int)V.t_end[t] - (int)V.t_start[t] : 0;
+    int64_t Lx = B.len[t];
+    uint32_t a = B.area[t], ms = B.msum[t], mc = B.mcnt[t];
+    uint64_t sh = B.sh[t];
+    int nf = B.nf[t];
     if (ch.any && t == ch.Ts) {
       Lx += ch.dLs;
       a -= ch.mv_area;
@@ -306,9 +324,8 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   uint32_t R[N], load[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    const bool live = t < nt;
-    hm[t] = live ? (HM)V.hu_mask[t] : (HM)0;
-    sm[t] = M128{live ? V.su_mask[2 * t] : 0ull, (SMALL || !live) ? 0ull : V.su_mask[2 * t + 1]};
+    hm[t] = (HM)B.hu_mask[t];
+    sm[t] = M128{B.su_lo[t], SMALL ? 0ull : B.su_hi[t]};
     R[t] = B.R[t];
     load[t] = B.load[t];
   }
