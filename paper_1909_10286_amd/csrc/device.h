@@ -38,6 +38,11 @@ __device__ __forceinline__ uint64_t udiv(uint64_t p, uint32_t q) {
   return (uint64_t)((double)p / (double)q);
 }
 
+// udiv with a 64-bit divisor: exact for p + q < 2^53, q > 0.
+__device__ __forceinline__ uint64_t udiv_wide(uint64_t p, uint64_t q) {
+  return (uint64_t)((double)p / (double)q);
+}
+
 // floor(n / d) for n < 2^31 and 0 < d < 2^16 from r = 1/d (double): n * r
 // is within 2^-19 of n / d, whose fraction is at most 1 - 2^-16, so the
 // truncation is floor(n / d) or one below it (exact quotients); one check,

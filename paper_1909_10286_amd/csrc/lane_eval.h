@@ -196,53 +196,37 @@ __device__ __forceinline__ tm_t lane_twait(const View &V, const LaneBase &B, con
   return (tm_t)udiv(7200ull * dm, V.su_speed[s]) - (tm_t)udiv_small(ld - V.su_fill[s], nhu, r);
 }
 
-// Lowest-index arg-max over active tours (gmax, top) and over the others
-// (g2, second); -1 when there is none.
-// (Branch-free: every step is a select, so the lanes of a wave never split.)
+// Rebalancing keys: a tour's value and index in one 32-bit integer,
+// (ord << 4) | (15 - t), where ord is the value clamped to [-2^26 - 1, 2^26].
+// Every finite value lies strictly inside that range (the narrow bound), so
+// the clamp only maps +inf to 2^26 and -inf to -2^26 - 1 and keeps the
+// order; an inactive tour takes ord = -2^26 - 1, below every active tour.
+// The largest key is then the lowest-index arg-max over active tours, and
+// key ^ 15 orders equal values by increasing index (the arg-min's rule).
+constexpr int32_t kOrdHi = 1 << 26, kOrdLo = -(1 << 26) - 1;
+__device__ __forceinline__ int32_t lkey(tm_t v, int t) {
+  const int32_t o = v < kOrdLo ? kOrdLo : (v > kOrdHi ? kOrdHi : v);
+  return (int32_t)(((uint32_t)o << 4) | (uint32_t)(15 - t));
+}
+__device__ __forceinline__ int32_t lkey_inactive(int t) { return lkey(kOrdLo, t); }
+__device__ __forceinline__ int32_t lkey_ord(int32_t k) { return k >> 4; }
+__device__ __forceinline__ tm_t lord_value(int32_t o) {
+  return o >= kOrdHi ? kTInf : (o <= kOrdLo ? kTNegInf : (tm_t)o);
+}
+__device__ __forceinline__ int32_t lmed3(int32_t a, int32_t b, int32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+// The three largest keys, m1 >= m2 >= m3 (INT32_MIN where N is smaller).
 template <int N>
-__device__ __forceinline__ void lane_top2(const tm_t (&v)[N], uint32_t actm, int &gmax, tm_t &top,
-                                          int &g2, tm_t &second) {
-  gmax = g2 = -1;
-  top = second = kTNegInf;
+__device__ __forceinline__ void lane_top3(const int32_t (&k)[N], int32_t &m1, int32_t &m2, int32_t &m3) {
+  m1 = m2 = m3 = INT32_MIN;
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    const bool a = (actm >> t) & 1u;
-    const bool up1 = a && (gmax < 0 || v[t] > top);
-    const bool up2 = a && !up1 && (g2 < 0 || v[t] > second);
-    g2 = up1 ? gmax : (up2 ? t : g2);
-    second = up1 ? top : (up2 ? v[t] : second);
-    gmax = up1 ? t : gmax;
-    top = up1 ? v[t] : top;
+    const int32_t x = k[t];
+    m3 = lmed3(m2, m3, x);
+    m2 = lmed3(m1, m2, x);
+    m1 = max(m1, x);
   }
-}
-
-template <int N>
-__device__ __forceinline__ tm_t lane_max(const tm_t (&v)[N], uint32_t actm) {
-  tm_t r = kTNegInf;
-#pragma unroll
-  for (int t = 0; t < N; ++t) r = (((actm >> t) & 1u) && v[t] > r) ? v[t] : r;
-  return r;
-}
-
-// Donors of a round: tours holding units outside {g_max, g2}, else outside
-// {g_max}; then the lowest-index arg-min of their key (the value of active
-// tours, -inf for inactive ones).  Returns -1 when there is no donor.
-template <int N>
-__device__ __forceinline__ int lane_gmin(const tm_t (&v)[N], uint32_t actm, uint32_t hasu, int gmax,
-                                         int g2) {
-  const uint32_t not_max = gmax >= 0 ? ~(1u << gmax) : ~0u, not_2 = g2 >= 0 ? ~(1u << g2) : ~0u;
-  const uint32_t d1 = hasu & not_max & not_2, d2 = hasu & not_max;
-  const uint32_t dm = d1 ? d1 : d2;
-  int g = -1;
-  tm_t best = 0;
-#pragma unroll
-  for (int t = 0; t < N; ++t) {
-    const tm_t k = ((actm >> t) & 1u) ? v[t] : kTNegInf;
-    const bool take = ((dm >> t) & 1u) && (g < 0 || k < best);
-    g = take ? t : g;
-    best = take ? k : best;
-  }
-  return g;
 }
 
 struct LaneOut {
@@ -351,25 +335,38 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
     }
   }
   uint32_t hu_moved = 0;   // tours whose HUs the rounds changed
+  // Rebalancing keys of the completion times (lkey).
+  int32_t KT[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) KT[t] = ((actm >> t) & 1u) ? lkey(T[t], t) : lkey_inactive(t);
   if (embedded) {
+    uint32_t hasu = 0;   // tours holding HUs
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      if (hm[t]) hasu |= 1u << t;
     int rounds = 0;
     while (true) {
-      int gmax, g2;
-      tm_t top, t2;
-      lane_top2(T, actm, gmax, top, g2, t2);
-      if (gmax < 0) break;
-      const bool has2 = g2 >= 0;
-      uint32_t hasu = 0;
+      int32_t m1, m2, m3;
+      lane_top3(KT, m1, m2, m3);
+      if (lkey_ord(m1) <= kOrdLo) break;   // no active tour
+      const int gmax = 15 - (m1 & 15);
+      const int t2 = 15 - (m2 & 15);        // the tour of the second key (15: none)
+      const bool has2 = lkey_ord(m2) > kOrdLo;
+      const tm_t c2 = lord_value(lkey_ord(m2));
+      const uint32_t nmax = hasu & ~(1u << gmax);
+      const uint32_t d1 = has2 ? nmax & ~(1u << t2) : nmax;
+      const uint32_t dmask = d1 ? d1 : nmax;
+      int32_t kmin = INT32_MAX;
 #pragma unroll
-      for (int t = 0; t < N; ++t)
-        if (hm[t]) hasu |= 1u << t;
-      const int gmin = lane_gmin(T, actm, hasu, gmax, g2);
-      if (gmin < 0) break;
+      for (int t = 0; t < N; ++t) kmin = min(kmin, ((dmask >> t) & 1u) ? (KT[t] ^ 15) : INT32_MAX);
+      if (kmin == INT32_MAX) break;
+      const int gmin = kmin & 15;
       if (rounds == (int)P.cap_hu) {
         o.flags |= kCandCapHu;
         break;
       }
-      HM cands = lpick(hm, gmin);
+      const HM hmin = lpick(hm, gmin);
+      HM cands = hmin;
       const uint32_t lcx = lpick(lc, gmax);
       const uint32_t ax = lpick(A, gmax), rx = lpick(R, gmax);
       int u = 0;
@@ -378,71 +375,88 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         u = lane_ffs(cands) - 1;
         cands &= cands - 1;
         trial = (tm_t)(lcx + (uint32_t)udiv(3600ull * ax, rx + V.hu_rate[u]));
-        if (!has2 || trial < t2 || cands == 0) break;
+        if (!has2 || trial < c2 || cands == 0) break;
       }
       const uint32_t ru = V.hu_rate[u];
       const HM bit = (HM)1 << u;
-      const tm_t Tmin0 = lpick(T, gmin), Tmax0 = lpick(T, gmax);
-      // The two tours that change, recomputed (inactive tours keep their value).
+      // The two tours that change, recomputed; an inactive g_min keeps its
+      // key, and g_max's new time is the trial of the unit moved (rates are
+      // positive).  The round is kept only if the largest time falls.
       const uint32_t Rmin = lpick(R, gmin) - ru, Rmax = rx + ru;
-      const tm_t Tmin1 = ((actm >> gmin) & 1u) ? lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin) : Tmin0;
-      // g_max's new time is the trial of the unit moved (rates are positive).
-      const tm_t Tmax1 = ((actm >> gmax) & 1u) ? trial : Tmax0;
-      // The new times of every tour, kept only if the maximum falls.
-      tm_t Tn[N];
-#pragma unroll
-      for (int t = 0; t < N; ++t) Tn[t] = t == gmin ? Tmin1 : (t == gmax ? Tmax1 : T[t]);
+      const int32_t kmin1 = ((actm >> gmin) & 1u)
+                                ? lkey(lane_tcompl(lpick(lc, gmin), lpick(A, gmin), Rmin), gmin)
+                                : (kmin ^ 15);
+      const int32_t kmax1 = lkey(trial, gmax);
+      const int32_t rest = gmin == t2 ? m3 : m2;
       ++rounds;
-      const bool keep = lane_max(Tn, actm) < top;
+      const bool keep = lkey_ord(max(rest, max(kmin1, kmax1))) < lkey_ord(m1);
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         const bool mn = keep && t == gmin, mx = keep && t == gmax;
         hm[t] = mn ? (hm[t] & ~bit) : (mx ? (hm[t] | bit) : hm[t]);
         R[t] = mn ? Rmin : (mx ? Rmax : R[t]);
-        T[t] = keep ? Tn[t] : T[t];
+        KT[t] = mn ? kmin1 : (mx ? kmax1 : KT[t]);
       }
       if (!keep) break;
+      hasu |= 1u << gmax;
+      if (!(hmin & ~bit)) hasu &= ~(1u << gmin);
       hu_moved |= (1u << gmin) | (1u << gmax);
     }
   }
-  const tm_t tmax = lane_max(T, actm);
+  // Makespan: the largest completion time over active tours.
+  int32_t kt_max = INT32_MIN;
+#pragma unroll
+  for (int t = 0; t < N; ++t) kt_max = max(kt_max, KT[t]);
+  const tm_t tmax = lkey_ord(kt_max) <= kOrdLo ? kTNegInf : lord_value(lkey_ord(kt_max));
   // ---- SU min-max rebalancing, Alg. 2: waiting time ----
   // Waiting times: the base's, but for the move's two tours and the tours
   // whose HU count the rounds changed.  The SU masks are still the base's,
-  // so a tour's critical SU and fill-time sum are the base's.
-  uint32_t nhu[N];
-  tm_t W[N];
+  // so a tour's critical SU and fill-time sum are the base's.  Per tour, the
+  // HU count and the mean distance share one word (nhu << 25 | dm; dm < 2^24,
+  // nhu <= 64), so that one select chain picks both.
+  uint32_t nd[N];
+  int32_t K[N];   // rebalancing keys of the waiting times (lkey)
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    nhu[t] = (uint32_t)lane_popc(hm[t]);
-    W[t] = B.W[t];
+    nd[t] = dm[t] | ((uint32_t)lane_popc(hm[t]) << 25);
+    K[t] = ((actm >> t) & 1u) ? lkey(B.W[t], t) : lkey_inactive(t);
   }
-  for (uint32_t redo = hu_moved | (1u << ch.Ts) | (1u << ch.Td); redo; redo &= redo - 1) {
+  for (uint32_t redo = (hu_moved | (1u << ch.Ts) | (1u << ch.Td)) & actm; redo; redo &= redo - 1) {
     const int g = lane_ffs(redo) - 1;
-    const uint32_t nh = lpick(nhu, g);
+    const uint32_t ndg = lpick(nd, g);
+    const uint32_t nh = ndg >> 25;
     const int s = B.top[g];
-    tm_t Wg = 0;
-    if ((actm >> g) & 1u)
-      Wg = (s < 0 || nh == 0) ? kTInf
-                              : (tm_t)udiv(7200ull * lpick(dm, g), V.su_speed[s]) -
-                                    (tm_t)udiv_small(B.load[g] - V.su_fill[s], nh, B.rcp[nh]);
+    const tm_t Wg = (s < 0 || nh == 0) ? kTInf
+                                       : (tm_t)udiv(7200ull * (ndg & 0x1FFFFFFu), V.su_speed[s]) -
+                                             (tm_t)udiv_small(B.load[g] - V.su_fill[s], nh, B.rcp[nh]);
+    const int32_t kg = lkey(Wg, g);
 #pragma unroll
-    for (int t = 0; t < N; ++t) W[t] = t == g ? Wg : W[t];
+    for (int t = 0; t < N; ++t) K[t] = t == g ? kg : K[t];
   }
   if (embedded) {
+    uint32_t hasu = 0;   // tours holding SUs
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      if (!m_empty(sm[t])) hasu |= 1u << t;
     int rounds = 0;
     while (true) {
-      int gmax, g2;
-      tm_t top, w2;
-      lane_top2(W, actm, gmax, top, g2, w2);
-      if (gmax < 0) break;
-      const bool has2 = g2 >= 0;
-      uint32_t hasu = 0;
+      int32_t m1, m2, m3;
+      lane_top3(K, m1, m2, m3);
+      if (lkey_ord(m1) <= kOrdLo) break;   // no active tour
+      const int gmax = 15 - (m1 & 15);
+      const int t2 = 15 - (m2 & 15);        // the tour of the second key (15: none)
+      const bool has2 = lkey_ord(m2) > kOrdLo;
+      const tm_t w2 = lord_value(lkey_ord(m2));
+      // Donors: tours holding units outside {g_max, g2}, else outside
+      // {g_max}; the arg-min of their keys (inactive tours lowest).
+      const uint32_t nmax = hasu & ~(1u << gmax);
+      const uint32_t d1 = has2 ? nmax & ~(1u << t2) : nmax;
+      const uint32_t dmask = d1 ? d1 : nmax;
+      int32_t kmin = INT32_MAX;
 #pragma unroll
-      for (int t = 0; t < N; ++t)
-        if (!m_empty(sm[t])) hasu |= 1u << t;
-      const int gmin = lane_gmin(W, actm, hasu, gmax, g2);
-      if (gmin < 0) break;
+      for (int t = 0; t < N; ++t) kmin = min(kmin, ((dmask >> t) & 1u) ? (K[t] ^ 15) : INT32_MAX);
+      if (kmin == INT32_MAX) break;
+      const int gmin = kmin & 15;
       if (rounds == (int)P.cap_su) {
         o.flags |= kCandCapSu;
         break;
@@ -458,52 +472,77 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         shi[t] = sm[t].hi;
       }
       const M128 cands_all{lpick(slo, gmin), lpick(shi, gmin)}, smx{lpick(slo, gmax), lpick(shi, gmax)};
-      M128 cands = cands_all;
       const int topx = m_empty(smx) ? -1 : m_top(smx);
-      const uint32_t ldx = lpick(load, gmax), nhx = lpick(nhu, gmax), dmx = lpick(dm, gmax);
+      const uint32_t ndx = lpick(nd, gmax);
+      const uint32_t ldx = lpick(load, gmax), nhx = ndx >> 25, dmx = ndx & 0x1FFFFFFu;
       const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
       const double r_nhx = B.rcp[nhx];
-      int u = 0;
-      tm_t trial = kTInf;   // g_max's waiting time with the unit tried last
-      while (!m_empty(cands)) {
-        u = m_pop_low(cands);
-        if (nhx == 0) {
-          trial = kTInf;
+      // The donor's units are tried in rank order: the first whose move takes
+      // g_max's waiting time below w2 moves, else the last (without g2 the
+      // first; without HUs every trial is infinite, so the last).  Each form
+      // of the trial falls below w2 exactly when one integer of the unit
+      // passes a bound formed once per round, so the scan compares integers
+      // and only the chosen unit's waiting time is computed:
+      //  - a unit ranked below g_max's critical SU topx leaves topx critical,
+      //    trial = rt_top - floor((C + f_u) / nhx) with C = ldx - f_topx: below
+      //    w2 iff f_u >= nhx * J - C, J = rt_top - w2 + 1 (every unit if J <= 0);
+      //  - a unit ranked above it becomes critical, trial = floor(7200 dmx /
+      //    v_u) - floor(ldx / nhx): below w2 iff K = w2 + floor(ldx / nhx) > 0
+      //    and v_u >= floor(7200 dmx / K) + 1.
+      // (All times are below 2^26 s here, so neither side wraps.)
+      int u;
+      {
+        M128 cands = cands_all;
+        if (!has2 || nhx == 0) {
+          u = has2 ? m_top(cands) : m_pop_low(cands);
         } else {
-          const int s = u > topx ? u : topx;
-          const uint32_t ld = ldx + V.su_fill[u];
-          const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
-          trial = (tm_t)rt - (tm_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
+          const int64_t J = (int64_t)rt_top - (int64_t)w2 + 1;
+          const uint32_t C = topx >= 0 ? ldx - V.su_fill[topx] : 0u;
+          const int64_t fa = J <= 0 ? 0 : (int64_t)nhx * J - (int64_t)C;
+          const uint32_t fbound = fa <= 0 ? 0u : (fa >= (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)fa);
+          const int64_t Kb = (int64_t)w2 + (int64_t)udiv_small(ldx, nhx, r_nhx);
+          const uint64_t vbound = Kb <= 0 ? ~0ull : udiv_wide(7200ull * dmx, (uint64_t)Kb) + 1ull;
+          while (true) {
+            u = m_pop_low(cands);
+            const bool ok = u < topx ? V.su_fill[u] >= fbound : (uint64_t)V.su_speed[u] >= vbound;
+            if (ok || m_empty(cands)) break;
+          }
         }
-        if (!has2 || trial < w2 || m_empty(cands)) break;
+      }
+      tm_t trial = kTInf;   // g_max's waiting time with unit u
+      if (nhx != 0) {
+        const int s = u > topx ? u : topx;
+        const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
+        trial = (tm_t)rt - (tm_t)udiv_small(ldx + V.su_fill[u] - V.su_fill[s], nhx, r_nhx);
       }
       const uint32_t fu = V.su_fill[u];
-      const tm_t Wmin0 = lpick(W, gmin), Wmax0 = lpick(W, gmax);
-      // The two tours after the move, then the new times of every tour, kept
-      // only if the maximum falls.
+      // The two tours after the move; the round is kept only if the largest
+      // waiting time over active tours falls.  g_max's new time is the trial
+      // of the unit moved (its critical SU is the larger of the two, its load
+      // and HU count as in the trial); an inactive g_min keeps its key.
       const uint64_t ulo = (SMALL || u < 64) ? 1ull << u : 0ull, uhi = (SMALL || u < 64) ? 0ull : 1ull << (u - 64);
       const M128 smin_new{cands_all.lo & ~ulo, cands_all.hi & ~uhi}, smax_new{smx.lo | ulo, smx.hi | uhi};
       const uint32_t ldmin = lpick(load, gmin) - fu;
-      const tm_t Wmin1 = ((actm >> gmin) & 1u)
-                                ? lane_twait(V, B, smin_new, ldmin, lpick(nhu, gmin), lpick(dm, gmin))
-                                : Wmin0;
-      // g_max's new time is the trial of the unit moved: its critical SU is
-      // the larger of the two, its load and HU count as in the trial.
-      const tm_t Wmax1 = ((actm >> gmax) & 1u) ? trial : Wmax0;
-      tm_t Wn[N];
-#pragma unroll
-      for (int t = 0; t < N; ++t) Wn[t] = t == gmin ? Wmin1 : (t == gmax ? Wmax1 : W[t]);
+      const uint32_t ndmin = lpick(nd, gmin);
+      const int32_t kmin1 = ((actm >> gmin) & 1u)
+                                ? lkey(lane_twait(V, B, smin_new, ldmin, ndmin >> 25, ndmin & 0x1FFFFFFu), gmin)
+                                : (kmin ^ 15);
+      const int32_t kmax1 = lkey(trial, gmax);
+      // The largest key outside {g_max, g_min}: m2, or m3 when g_min holds m2.
+      const int32_t rest = gmin == t2 ? m3 : m2;
       ++rounds;
-      const bool keep = lane_max(Wn, actm) < top;
+      const bool keep = lkey_ord(max(rest, max(kmin1, kmax1))) < lkey_ord(m1);
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         const bool mn = keep && t == gmin, mx = keep && t == gmax;
         sm[t].lo = mn ? smin_new.lo : (mx ? smax_new.lo : sm[t].lo);
         sm[t].hi = mn ? smin_new.hi : (mx ? smax_new.hi : sm[t].hi);
         load[t] = mn ? ldmin : (mx ? ldx + fu : load[t]);
-        W[t] = keep ? Wn[t] : W[t];
+        K[t] = mn ? kmin1 : (mx ? kmax1 : K[t]);
       }
       if (!keep) break;
+      hasu |= 1u << gmax;
+      if (m_empty(smin_new)) hasu &= ~(1u << gmin);
     }
   }
   // ---- path length (sec. 2.2) ----
