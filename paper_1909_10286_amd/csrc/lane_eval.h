@@ -45,6 +45,11 @@ struct LaneBase {
   uint32_t lc[kLaneMaxTours];  // floor(3600 L / v_HU)
   tm_t T[kLaneMaxTours];       // completion time (0 for an inactive tour)
   tm_t W[kLaneMaxTours];       // waiting time, eq. (5) (0 for an inactive tour)
+  uint32_t dm[kLaneMaxTours];  // mean field-BP distance (Alg. 2), 0 without fields
+  int32_t KT[kLaneMaxTours];   // rebalancing keys (lkey) of T and W
+  int32_t KW[kLaneMaxTours];
+  uint32_t actm;               // tours with fields
+  uint64_t shsum;              // shuttle distance over all tours
   double rcp[kMaxHus + 1];   // rcp[k] = 1/k (k >= 1): the reciprocals udiv_small takes
 };
 
@@ -52,13 +57,33 @@ __device__ __forceinline__ tm_t lane_tcompl(uint32_t lc, uint32_t A, uint32_t ra
   return rate == 0 ? kTInf : (tm_t)(lc + (uint32_t)udiv(3600ull * A, rate));
 }
 
+// Rebalancing keys: a tour's value and index in one 32-bit integer,
+// (ord << 4) | (15 - t), where ord is the value clamped to [-2^26 - 1, 2^26].
+// Every finite value lies strictly inside that range (the narrow bound), so
+// the clamp only maps +inf to 2^26 and -inf to -2^26 - 1 and keeps the
+// order; an inactive tour takes ord = -2^26 - 1, below every active tour.
+// The largest key is then the lowest-index arg-max over active tours, and
+// key ^ 15 orders equal values by increasing index (the arg-min's rule).
+constexpr int32_t kOrdHi = 1 << 26, kOrdLo = -(1 << 26) - 1;
+__device__ __forceinline__ int32_t lkey(tm_t v, int t) {
+  const int32_t o = v < kOrdLo ? kOrdLo : (v > kOrdHi ? kOrdHi : v);
+  return (int32_t)(((uint32_t)o << 4) | (uint32_t)(15 - t));
+}
+__device__ __forceinline__ int32_t lkey_inactive(int t) { return lkey(kOrdLo, t); }
+__device__ __forceinline__ int32_t lkey_ord(int32_t k) { return k >> 4; }
+__device__ __forceinline__ tm_t lord_value(int32_t o) {
+  return o >= kOrdHi ? kTInf : (o <= kOrdLo ? kTNegInf : (tm_t)o);
+}
+__device__ __forceinline__ int32_t lmed3(int32_t a, int32_t b, int32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
 // Fills `B` for the tours 0..nt-1 of the base in V (zero and inactive
 // beyond), and the reciprocal table.  Called by a whole workgroup; the caller
 // synchronises before and after.
 __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const InstParams &P, int nt) {
   if (threadIdx.x < kLaneMaxTours) {
     const int t = threadIdx.x;
-    uint32_t R = 0, ld = 0, lc = 0, nhu = 0;
+    uint32_t R = 0, ld = 0, lc = 0, nhu = 0, dm = 0;
     int top = -1;
     tm_t T = 0, W = 0;
     if (t < nt) {
@@ -72,7 +97,8 @@ __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const
       lc = (uint32_t)udiv(3600ull * V.t_len[t], P.v_hu);
       if ((int)V.t_end[t] > (int)V.t_start[t]) {
         T = lane_tcompl(lc, V.t_area[t], R);
-        const uint32_t mc = V.t_mcnt[t], dm = mc ? V.t_msum[t] / mc : 0u;
+        const uint32_t mc = V.t_mcnt[t];
+        dm = mc ? V.t_msum[t] / mc : 0u;
         W = (top < 0 || nhu == 0) ? kTInf
                                   : (tm_t)udiv(7200ull * dm, V.su_speed[top]) - (tm_t)udiv(ld - V.su_fill[top], nhu);
       }
@@ -93,6 +119,20 @@ __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const
     B.lc[t] = lc;
     B.T[t] = T;
     B.W[t] = W;
+    B.dm[t] = dm;
+    const bool act = live && (int)V.t_end[t] > (int)V.t_start[t];
+    B.KT[t] = act ? lkey(T, t) : lkey_inactive(t);
+    B.KW[t] = act ? lkey(W, t) : lkey_inactive(t);
+  }
+  if (threadIdx.x == 0) {
+    uint32_t actm = 0;
+    uint64_t shsum = 0;
+    for (int t = 0; t < nt; ++t) {
+      if ((int)V.t_end[t] > (int)V.t_start[t]) actm |= 1u << t;
+      shsum += V.t_sh[t];
+    }
+    B.actm = actm;
+    B.shsum = shsum;
   }
   for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) B.rcp[k] = k ? 1.0 / (double)k : 0.0;
 }
@@ -196,26 +236,6 @@ __device__ __forceinline__ tm_t lane_twait(const View &V, const LaneBase &B, con
   return (tm_t)udiv(7200ull * dm, V.su_speed[s]) - (tm_t)udiv_small(ld - V.su_fill[s], nhu, r);
 }
 
-// Rebalancing keys: a tour's value and index in one 32-bit integer,
-// (ord << 4) | (15 - t), where ord is the value clamped to [-2^26 - 1, 2^26].
-// Every finite value lies strictly inside that range (the narrow bound), so
-// the clamp only maps +inf to 2^26 and -inf to -2^26 - 1 and keeps the
-// order; an inactive tour takes ord = -2^26 - 1, below every active tour.
-// The largest key is then the lowest-index arg-max over active tours, and
-// key ^ 15 orders equal values by increasing index (the arg-min's rule).
-constexpr int32_t kOrdHi = 1 << 26, kOrdLo = -(1 << 26) - 1;
-__device__ __forceinline__ int32_t lkey(tm_t v, int t) {
-  const int32_t o = v < kOrdLo ? kOrdLo : (v > kOrdHi ? kOrdHi : v);
-  return (int32_t)(((uint32_t)o << 4) | (uint32_t)(15 - t));
-}
-__device__ __forceinline__ int32_t lkey_inactive(int t) { return lkey(kOrdLo, t); }
-__device__ __forceinline__ int32_t lkey_ord(int32_t k) { return k >> 4; }
-__device__ __forceinline__ tm_t lord_value(int32_t o) {
-  return o >= kOrdHi ? kTInf : (o <= kOrdLo ? kTNegInf : (tm_t)o);
-}
-__device__ __forceinline__ int32_t lmed3(int32_t a, int32_t b, int32_t c) {
-  return max(min(a, b), min(max(a, b), c));
-}
 // The three largest keys, m1 >= m2 >= m3 (INT32_MIN where N is smaller).
 template <int N>
 __device__ __forceinline__ void lane_top3(const int32_t (&k)[N], int32_t &m1, int32_t &m2, int32_t &m3) {
@@ -272,36 +292,47 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   o.feasible = true;
   const Change ch = move_change(V, P, m, nb);
   // ---- tours of the candidate ----
-  uint32_t L[N], A[N], dm[N];
-  uint32_t actm = 0;
-  uint64_t shsum = 0;
+  // The move changes its two tours (one, when both ends lie in the same
+  // tour); every other tour keeps the base's values.
+  const int Ts = ch.Ts, Td = ch.Td;
+  const bool same = Ts == Td;
+  uint32_t LS = 0, LD = 0, AS = 0, AD = 0, dmS = 0, dmD = 0;
+  uint32_t actm = B.actm;
+  uint64_t shsum = B.shsum;
+  if (ch.any) {
+    const int64_t dS = ch.dLs + (same ? ch.dLd : 0), dD = ch.dLd + (same ? ch.dLs : 0);
+    LS = (uint32_t)((int64_t)B.len[Ts] + dS);
+    LD = (uint32_t)((int64_t)B.len[Td] + dD);
+    AS = same ? B.area[Ts] : B.area[Ts] - ch.mv_area;
+    AD = same ? B.area[Td] : B.area[Td] + ch.mv_area;
+    const int32_t msS = ch.ms_s + (same ? ch.ms_d : 0), mcS = ch.mc_s + (same ? ch.mc_d : 0);
+    const int32_t msD = ch.ms_d + (same ? ch.ms_s : 0), mcD = ch.mc_d + (same ? ch.mc_s : 0);
+    const uint32_t ms1 = (uint32_t)((int32_t)B.msum[Ts] + msS), mc1 = (uint32_t)((int32_t)B.mcnt[Ts] + mcS);
+    const uint32_t ms2 = (uint32_t)((int32_t)B.msum[Td] + msD), mc2 = (uint32_t)((int32_t)B.mcnt[Td] + mcD);
+    dmS = mc1 ? ms1 / mc1 : 0u;
+    dmD = mc2 ? ms2 / mc2 : 0u;
+    const int nfS = B.nf[Ts] - (same ? 0 : (int)ch.mv_nf), nfD = B.nf[Td] + (same ? 0 : (int)ch.mv_nf);
+    actm = (actm & ~(1u << Ts) & ~(1u << Td)) | ((nfS > 0 ? 1u : 0u) << Ts) | ((nfD > 0 ? 1u : 0u) << Td);
+    shsum = shsum - ch.sh_out + ch.sh_in;
+  }
+  // Road and completion times of the two tours (the base's where the move
+  // changes nothing).
+  const uint32_t lcS = ch.any ? (uint32_t)udiv(3600ull * LS, P.v_hu) : 0u;
+  const uint32_t lcD = ch.any ? (uint32_t)udiv(3600ull * LD, P.v_hu) : 0u;
+  const int32_t ktS = ((actm >> Ts) & 1u) ? lkey(lane_tcompl(lcS, AS, B.R[Ts]), Ts) : lkey_inactive(Ts);
+  const int32_t ktD = ((actm >> Td) & 1u) ? lkey(lane_tcompl(lcD, AD, B.R[Td]), Td) : lkey_inactive(Td);
+  // One pass over the tours, so that the comparisons with the move's tours
+  // die with it.
+  uint32_t L[N], A[N], dm[N], lc[N];
+  int32_t KT[N];   // rebalancing keys of the completion times (lkey)
 #pragma unroll
   for (int t = 0; t < N; ++t) {
-    int64_t Lx = B.len[t];
-    uint32_t a = B.area[t], ms = B.msum[t], mc = B.mcnt[t];
-    uint64_t sh = B.sh[t];
-    int nf = B.nf[t];
-    if (ch.any && t == ch.Ts) {
-      Lx += ch.dLs;
-      a -= ch.mv_area;
-      sh -= ch.sh_out;
-      ms = (uint32_t)((int32_t)ms + ch.ms_s);
-      mc = (uint32_t)((int32_t)mc + ch.mc_s);
-      nf -= (int)ch.mv_nf;
-    }
-    if (ch.any && t == ch.Td) {
-      Lx += ch.dLd;
-      a += ch.mv_area;
-      sh += ch.sh_in;
-      ms = (uint32_t)((int32_t)ms + ch.ms_d);
-      mc = (uint32_t)((int32_t)mc + ch.mc_d);
-      nf += (int)ch.mv_nf;
-    }
-    L[t] = (uint32_t)Lx;
-    A[t] = a;
-    dm[t] = mc ? ms / mc : 0u;
-    if (nf > 0) actm |= 1u << t;
-    shsum += sh;
+    const bool isS = ch.any && t == Ts, isD = ch.any && t == Td;
+    L[t] = isS ? LS : (isD ? LD : B.len[t]);
+    A[t] = isS ? AS : (isD ? AD : B.area[t]);
+    dm[t] = isS ? dmS : (isD ? dmD : B.dm[t]);
+    lc[t] = isS ? lcS : (isD ? lcD : B.lc[t]);
+    KT[t] = isS ? ktS : (isD ? ktD : B.KT[t]);
   }
   HM hm[N];
   M128 sm[N];
@@ -315,30 +346,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   }
   const bool embedded = !(P.flags & kNoEmbeddedMin);
   // ---- HU min-max rebalancing: completion time ----
-  // Every tour but the move's two keeps the base's road and completion times.
-  uint32_t lc[N];
-  tm_t T[N];
-#pragma unroll
-  for (int t = 0; t < N; ++t) {
-    lc[t] = B.lc[t];
-    T[t] = B.T[t];
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int g = j == 0 ? ch.Ts : ch.Td;
-    const uint32_t lcg = (uint32_t)udiv(3600ull * lpick(L, g), P.v_hu);
-    const tm_t Tg = ((actm >> g) & 1u) ? lane_tcompl(lcg, lpick(A, g), B.R[g]) : 0;
-#pragma unroll
-    for (int t = 0; t < N; ++t) {
-      lc[t] = t == g ? lcg : lc[t];
-      T[t] = t == g ? Tg : T[t];
-    }
-  }
   uint32_t hu_moved = 0;   // tours whose HUs the rounds changed
-  // Rebalancing keys of the completion times (lkey).
-  int32_t KT[N];
-#pragma unroll
-  for (int t = 0; t < N; ++t) KT[t] = ((actm >> t) & 1u) ? lkey(T[t], t) : lkey_inactive(t);
   if (embedded) {
     uint32_t hasu = 0;   // tours holding HUs
 #pragma unroll
@@ -414,14 +422,17 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   // so a tour's critical SU and fill-time sum are the base's.  Per tour, the
   // HU count and the mean distance share one word (nhu << 25 | dm; dm < 2^24,
   // nhu <= 64), so that one select chain picks both.
+  // The base's keys, recomputed for the move's two tours (inactive ones
+  // take the inactive key) and the tours whose HU count changed.
   uint32_t nd[N];
   int32_t K[N];   // rebalancing keys of the waiting times (lkey)
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     nd[t] = dm[t] | ((uint32_t)lane_popc(hm[t]) << 25);
-    K[t] = ((actm >> t) & 1u) ? lkey(B.W[t], t) : lkey_inactive(t);
+    K[t] = B.KW[t];
   }
-  for (uint32_t redo = (hu_moved | (1u << ch.Ts) | (1u << ch.Td)) & actm; redo; redo &= redo - 1) {
+  const uint32_t moved = ch.any ? (1u << Ts) | (1u << Td) : 0u;
+  for (uint32_t redo = (hu_moved & actm) | moved; redo; redo &= redo - 1) {
     const int g = lane_ffs(redo) - 1;
     const uint32_t ndg = lpick(nd, g);
     const uint32_t nh = ndg >> 25;
@@ -429,7 +440,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
     const tm_t Wg = (s < 0 || nh == 0) ? kTInf
                                        : (tm_t)udiv(7200ull * (ndg & 0x1FFFFFFu), V.su_speed[s]) -
                                              (tm_t)udiv_small(B.load[g] - V.su_fill[s], nh, B.rcp[nh]);
-    const int32_t kg = lkey(Wg, g);
+    const int32_t kg = ((actm >> g) & 1u) ? lkey(Wg, g) : lkey_inactive(g);
 #pragma unroll
     for (int t = 0; t < N; ++t) K[t] = t == g ? kg : K[t];
   }
