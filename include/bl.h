@@ -165,6 +165,20 @@ const char *bl_last_error(const bl_ctx *ctx);
  * Writes its id to *inst.  Synchronising. */
 bl_status bl_instance_upload(bl_ctx *ctx, const bl_instance *in, int32_t *inst);
 
+/* How an uploaded instance is evaluated.  lane_eval: 1 when the evaluation
+ * takes one candidate per lane (at most 12 tours, time bounds within 32
+ * bits, no BL_SEGMENT_EVAL / BL_FULL_WALK / BL_WIDE_KEYS); tail_table: 1 when
+ * the second pass of that evaluation keeps every thread's SU masks in LDS
+ * (chosen at upload where it keeps the workgroups per CU; the environment
+ * variable BL_LANE_TAIL=0 at upload turns it off); wg_per_cu: workgroups per
+ * CU of the search evaluation; image_bytes: the instance image that every
+ * evaluating workgroup stages in LDS.  No device work. */
+typedef struct {
+  int32_t lane_eval, tail_table, wg_per_cu;
+  uint32_t image_bytes;
+} bl_instance_info;
+bl_status bl_instance_info_get(bl_ctx *ctx, int32_t inst, bl_instance_info *out);
+
 /* The initial solution of Algorithm 1 on the host: BPs to tours by one nearest-neighbour
  * chain from HQ (floor(n_bps / n_tours) per tour, residual to the last),
  * fields in id order to the closest BP with unmet demand (then the closest

@@ -57,6 +57,11 @@ class _SearchState(C.Structure):
                 ("t_best_s", C.c_int64)]
 
 
+class _InstanceInfo(C.Structure):
+    _fields_ = [("lane_eval", C.c_int32), ("tail_table", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("image_bytes", C.c_uint32)]
+
+
 class _SurConfig(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
                 ("max_examples", C.c_uint32), ("c0_m", C.c_float), ("t0_s", C.c_float)]
@@ -89,6 +94,7 @@ _SIGS = {
     "bl_status_str": (C.c_char_p, [C.c_int32]),
     "bl_last_error": (C.c_char_p, [C.c_void_p]),
     "bl_instance_upload": (C.c_int32, [C.c_void_p, C.POINTER(_Instance), C.POINTER(C.c_int32)]),
+    "bl_instance_info_get": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_InstanceInfo)]),
     "bl_init_solution": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(_Solution)]),
     "bl_solution_upload": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]),
     "bl_solution_download": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]),
@@ -308,6 +314,13 @@ class Context:
     def search_step(self, inst_id: int, seed: int, eps_threshold: int, n: int, inst_index: int = 0):
         p = _SearchParams(seed, eps_threshold, n, inst_index)
         self._check(self._lib.bl_search_step(self._h, inst_id, C.byref(p)))
+
+    def instance_info(self, inst_id: int) -> dict:
+        """How the instance is evaluated (bl_instance_info_get)."""
+        s = _InstanceInfo()
+        self._check(self._lib.bl_instance_info_get(self._h, inst_id, C.byref(s)))
+        return dict(lane_eval=s.lane_eval, tail_table=s.tail_table, wg_per_cu=s.wg_per_cu,
+                    image_bytes=s.image_bytes)
 
     def search_state(self, inst_id: int) -> dict:
         s = _SearchState()

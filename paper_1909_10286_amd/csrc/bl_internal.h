@@ -119,6 +119,7 @@ struct InstParams {
   uint32_t *defer_cnt; // [2] their counts per class
   uint32_t defer_cap;  // entries per class; 0: no deferral
   uint32_t defer_zeroed; // host side: the base preparation of this iteration already cleared the count
+  int32_t lane_tail;   // host side: the second lane pass keeps the SU masks in LDS (k_eval_lane_tail)
   uint16_t *hu_id;     // rank -> HU id
   uint16_t *su_id;     // rank -> SU id
 };
@@ -169,6 +170,10 @@ size_t eval_lds_bytes(const InstParams &P);
 // Whether the evaluation launches take one candidate per lane (instances of
 // at most 12 tours, unless a flag asks for the segment version).
 bool lane_eval_on(const InstParams &P);
+// Whether the second lane pass can take the kernel that keeps every
+// thread's SU masks in LDS without losing workgroups per CU (off with the
+// environment variable BL_LANE_TAIL=0).
+bool lane_tail_on(const InstParams &P);
 int eval_occupancy(const InstParams &P, bool search);
 size_t batch_lds_bytes(uint32_t max_image_words);
 int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small, bool feas_queue);

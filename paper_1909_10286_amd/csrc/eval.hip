@@ -127,6 +127,21 @@ __device__ __forceinline__ void lane_write(uint32_t c, const CandResult &r, uint
   if (out_flags) out_flags[c] = (uint8_t)r.flags;
 }
 
+// A candidate's outputs from its evaluation: key (cost, then index; none
+// when gated or infeasible), cost in km, makespan and flags.
+__device__ __forceinline__ CandResult lane_result(const LaneOut &o, uint32_t ci, int64_t t_star, uint32_t flags) {
+  CandResult r{kInfKey, __builtin_inff(), 0x7FFFFFFF, o.flags};
+  if (o.feasible) {
+    r.cost_km = (float)((double)o.cost / 1000.0);
+    r.mk = o.makespan >= 0x7FFFFFFFll ? 0x7FFFFFFF : (int32_t)o.makespan;
+    if (is_gated(o.makespan, t_star, flags))
+      r.flags |= kCandGated;
+    else
+      r.key = (o.cost << 24) | (uint64_t)ci;
+  }
+  return r;
+}
+
 // Waves per SIMD the lane kernel is compiled for: 2 (at most 256 VGPRs).
 // Left to itself the compiler takes 264 registers at 10 tours and drops to
 // one wave (clust500: 1.72 ms per evaluation step against 1.19 ms bounded);
@@ -198,15 +213,7 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
         return;
       }
     }
-    r.flags = o.flags;
-    if (o.feasible) {
-      r.cost_km = (float)((double)o.cost / 1000.0);
-      r.mk = o.makespan >= 0x7FFFFFFFll ? 0x7FFFFFFF : (int32_t)o.makespan;
-      if (is_gated(o.makespan, t_star, P.flags))
-        r.flags |= kCandGated;
-      else
-        r.key = (o.cost << 24) | (uint64_t)ci;
-    }
+    r = lane_result(o, ci, t_star, P.flags);
     lane_write<MODE>(c, r, out_key, out_cost, out_mk, out_flags);
     best = r.key < best ? r.key : best;
   };
@@ -282,6 +289,53 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
         }
       }
     }
+  }
+  if (MODE != kModeBatch) wave_min_to(best, P.best_key);
+}
+
+// The second pass over the deferred list where the SU masks of every thread
+// fit in LDS beside the image (rows of N entries after it, ltbl_get): a
+// round then reads and writes the two tours' masks in LDS instead of
+// selecting over every tour's registers.  Every deferred candidate passed
+// eq. (2), so the pass needs no queue, and nothing is deferred again.
+template <int N, bool SMALL, int MODE>
+__global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane_tail(InstParams P, const uint64_t *__restrict__ moves,
+                                                        uint32_t n, int64_t t_star_arg, uint64_t seed,
+                                                        uint32_t inst_index, uint64_t *__restrict__ out_key,
+                                                        float *__restrict__ out_cost,
+                                                        int32_t *__restrict__ out_mk,
+                                                        uint8_t *__restrict__ out_flags,
+                                                        const uint32_t *__restrict__ gather,
+                                                        const uint32_t *__restrict__ run_flag) {
+  if (run_flag && *run_flag == 0u) return;
+  const uint32_t cap = P.defer_cap;
+  const uint32_t n_bp = min(P.defer_cnt[0], cap);
+  const uint32_t total = n_bp + min(P.defer_cnt[1], cap);
+  if (blockIdx.x * blockDim.x >= total) return;
+  __shared__ LaneBase s_base;
+  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
+  stage(lds, P.image, P.lay.total_words);
+  __syncthreads();
+  const View V = make_view(lds, P.lay, P.dist);
+  lane_base_fill(s_base, V, P, N);
+  __syncthreads();
+  uint64_t *row0 = reinterpret_cast<uint64_t *>(lds + round4(P.lay.total_words)) + (SMALL ? 1 : 2) * threadIdx.x;
+  uint32_t it = 0;
+  int64_t t_star = t_star_arg;
+  if (MODE != kModeBatch) {
+    it = P.st->it;
+    t_star = P.st->t_best;
+  }
+  uint64_t best = kInfKey;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const uint32_t c = P.defer[i < n_bp ? i : cap + (i - n_bp)];
+    const uint32_t ci = MODE == kModeGather ? gather[c] : c;
+    const uint64_t w = MODE == kModeBatch ? moves[c] : draw_move(seed, ci, it, inst_index, V, P);
+    const Move m = decode_move(w, V, P);
+    const LaneOut o = eval_lane<N, SMALL, true>(V, P, s_base, m, 0, row0);
+    const CandResult r = lane_result(o, ci, t_star, P.flags);
+    lane_write<MODE>(c, r, out_key, out_cost, out_mk, out_flags);
+    best = r.key < best ? r.key : best;
   }
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
@@ -921,8 +975,28 @@ hipError_t launch_generate(const InstParams &P, uint64_t seed, uint32_t iter, ui
 size_t lane_lds_bytes(const InstParams &P) { return (size_t)round4(P.lay.total_words) * 4; }
 bool lane_small(const InstParams &P) { return P.NHU <= 32 && P.NSU <= 64; }
 
+size_t lane_tail_lds_bytes(const InstParams &P, bool small) {
+  return lane_lds_bytes(P) + (size_t)P.NT * 256 * (small ? ltbl_entry_bytes<true>() : ltbl_entry_bytes<false>());
+}
+
+template <int MODE, bool SMALL, class... A>
+hipError_t launch_lane_tail(const InstParams &P, int grid, hipStream_t s, A... a) {
+  const size_t lds = lane_tail_lds_bytes(P, SMALL);
+  switch (P.NT) {
+#define BL_TAIL_CASE(N) \
+    case N: hipLaunchKernelGGL((k_eval_lane_tail<N, SMALL, MODE>), dim3(grid), dim3(256), lds, s, P, a...); break;
+    BL_TAIL_CASE(1) BL_TAIL_CASE(2) BL_TAIL_CASE(3) BL_TAIL_CASE(4)
+    BL_TAIL_CASE(5) BL_TAIL_CASE(6) BL_TAIL_CASE(7) BL_TAIL_CASE(8)
+    BL_TAIL_CASE(9) BL_TAIL_CASE(10) BL_TAIL_CASE(11) BL_TAIL_CASE(12)
+#undef BL_TAIL_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int MODE, bool SMALL, class... A>
 hipError_t launch_lane_phase(const InstParams &P, int phase, int grid, hipStream_t s, A... a) {
+  if (phase == 1 && P.lane_tail) return launch_lane_tail<MODE, SMALL>(P, grid, s, a...);
   const size_t lds = lane_lds_bytes(P);
   switch (P.NT) {
 #define BL_LANE_CASE(N) \
@@ -1054,6 +1128,33 @@ int lane_occupancy(const InstParams &P, size_t lds) {
     default: break;
   }
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <bool SMALL>
+int lane_tail_occupancy(const InstParams &P, size_t lds) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (P.NT) {
+#define BL_TAIL_OCC(N) \
+    case N: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eval_lane_tail<N, SMALL, kModeSearch>, 256, lds); break;
+    BL_TAIL_OCC(1) BL_TAIL_OCC(2) BL_TAIL_OCC(3) BL_TAIL_OCC(4)
+    BL_TAIL_OCC(5) BL_TAIL_OCC(6) BL_TAIL_OCC(7) BL_TAIL_OCC(8)
+    BL_TAIL_OCC(9) BL_TAIL_OCC(10) BL_TAIL_OCC(11) BL_TAIL_OCC(12)
+#undef BL_TAIL_OCC
+    default: break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+bool lane_tail_on(const InstParams &P) {
+  if (!lane_eval_on(P)) return false;
+  if (const char *env = getenv("BL_LANE_TAIL"))
+    if (atoi(env) == 0) return false;
+  const bool small = lane_small(P);
+  const size_t lds = lane_tail_lds_bytes(P, small);
+  if (lds > 160 * 1024) return false;
+  const int occ = small ? lane_tail_occupancy<true>(P, lds) : lane_tail_occupancy<false>(P, lds);
+  return occ > 0 && occ >= eval_occupancy(P, true);
 }
 
 int eval_occupancy(const InstParams &P, bool search) {

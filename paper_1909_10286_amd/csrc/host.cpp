@@ -719,6 +719,7 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   }
   R->occ_batch = eval_occupancy(P, false);
   R->occ_search = eval_occupancy(P, true);
+  P.lane_tail = lane_tail_on(P) ? 1 : 0;
   c->inst.push_back(std::move(I));
   *inst_id = (int32_t)c->inst.size() - 1;
   return BL_OK;
@@ -923,6 +924,17 @@ bl_status bl_search_step(bl_ctx *c, int32_t id, const bl_search_params *p) {
   if (p->eps_threshold > (1ull << 32)) return fail(c, BL_EINVAL, "eps_threshold > 2^32");
   HIP_TRY(c, hipSetDevice(c->device));
   return search_step_on(c, I, p, work_stream(c));
+}
+
+bl_status bl_instance_info_get(bl_ctx *c, int32_t id, bl_instance_info *out) {
+  Instance *I = get_inst(c, id);
+  if (!I) return fail(c, BL_EINVAL, "bad instance id %d", id);
+  if (!out) return fail(c, BL_EINVAL, "null output");
+  out->lane_eval = lane_eval_on(I->P) ? 1 : 0;
+  out->tail_table = I->P.lane_tail ? 1 : 0;
+  out->wg_per_cu = I->occ_search;
+  out->image_bytes = I->P.lay.total_words * 4u;
+  return BL_OK;
 }
 
 bl_status bl_search_state_get(bl_ctx *c, int32_t id, bl_search_state *out) {

@@ -49,6 +49,7 @@ struct LaneBase {
   int32_t KT[kLaneMaxTours];   // rebalancing keys (lkey) of T and W
   int32_t KW[kLaneMaxTours];
   uint32_t actm;               // tours with fields
+  uint32_t su_has;             // tours holding SUs
   uint64_t shsum;              // shuttle distance over all tours
   double rcp[kMaxHus + 1];   // rcp[k] = 1/k (k >= 1): the reciprocals udiv_small takes
 };
@@ -125,13 +126,15 @@ __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const
     B.KW[t] = act ? lkey(W, t) : lkey_inactive(t);
   }
   if (threadIdx.x == 0) {
-    uint32_t actm = 0;
+    uint32_t actm = 0, su_has = 0;
     uint64_t shsum = 0;
     for (int t = 0; t < nt; ++t) {
       if ((int)V.t_end[t] > (int)V.t_start[t]) actm |= 1u << t;
+      if ((V.su_mask[2 * t] | V.su_mask[2 * t + 1]) != 0) su_has |= 1u << t;
       shsum += V.t_sh[t];
     }
     B.actm = actm;
+    B.su_has = su_has;
     B.shsum = shsum;
   }
   for (int k = threadIdx.x; k <= kMaxHus; k += blockDim.x) B.rcp[k] = k ? 1.0 / (double)k : 0.0;
@@ -262,6 +265,31 @@ __device__ __forceinline__ int lane_popc(uint64_t x) { return __popcll((unsigned
 __device__ __forceinline__ int lane_ffs(uint32_t x) { return __ffs(x); }
 __device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned long long)x); }
 
+// A lane's SU masks kept in LDS instead of registers: a table of N rows of
+// 256 entries (one per thread of the workgroup), `row0` pointing at the
+// lane's entry of row 0.  One 64-bit word per entry when SMALL, two
+// otherwise.  Reading or writing a tour's mask is then one LDS access
+// instead of a select over every tour; the banks a wave touches do not
+// depend on the tours its lanes pick.
+template <bool SMALL>
+__device__ __forceinline__ M128 ltbl_get(const uint64_t *row0, int t) {
+  if constexpr (SMALL) {
+    return M128{row0[t * 256], 0ull};
+  } else {
+    const ulonglong2 x = reinterpret_cast<const ulonglong2 *>(row0)[t * 256];
+    return M128{x.x, x.y};
+  }
+}
+template <bool SMALL>
+__device__ __forceinline__ void ltbl_set(uint64_t *row0, int t, const M128 &m) {
+  if constexpr (SMALL)
+    row0[t * 256] = m.lo;
+  else
+    reinterpret_cast<ulonglong2 *>(row0)[t * 256] = ulonglong2{m.lo, m.hi};
+}
+template <bool SMALL>
+constexpr size_t ltbl_entry_bytes() { return SMALL ? 8 : 16; }
+
 // SMALL: at most 32 HUs and 64 SUs, so that an HU mask is one 32-bit word
 // and an SU mask one 64-bit word (the high half of M128 stays zero, which
 // the compiler folds away).
@@ -274,9 +302,12 @@ __device__ __forceinline__ int lane_ffs(uint64_t x) { return __ffsll((unsigned l
 // inactive and as holding no units (lane_base_fill): they are then never
 // g_max, g2 or a donor, add nothing to the cost, and the result is that of
 // N = the tour count.
-template <int N, bool SMALL>
+//
+// TBL: the SU masks live in the LDS table at `row0` (ltbl_get) during the
+// SU rounds; the rows are written at their start.
+template <int N, bool SMALL, bool TBL = false>
 __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P, const LaneBase &B,
-                                             const Move &m, int su_limit) {
+                                             const Move &m, int su_limit, uint64_t *row0 = nullptr) {
   using HM = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
   LaneOut o;
   o.flags = 0;
@@ -340,7 +371,7 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
 #pragma unroll
   for (int t = 0; t < N; ++t) {
     hm[t] = (HM)B.hu_mask[t];
-    sm[t] = M128{B.su_lo[t], SMALL ? 0ull : B.su_hi[t]};
+    if constexpr (!TBL) sm[t] = M128{B.su_lo[t], SMALL ? 0ull : B.su_hi[t]};
     R[t] = B.R[t];
     load[t] = B.load[t];
   }
@@ -446,9 +477,15 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   }
   if (embedded) {
     uint32_t hasu = 0;   // tours holding SUs
+    if constexpr (TBL) {
+      hasu = B.su_has;
 #pragma unroll
-    for (int t = 0; t < N; ++t)
-      if (!m_empty(sm[t])) hasu |= 1u << t;
+      for (int t = 0; t < N; ++t) ltbl_set<SMALL>(row0, t, M128{B.su_lo[t], SMALL ? 0ull : B.su_hi[t]});
+    } else {
+#pragma unroll
+      for (int t = 0; t < N; ++t)
+        if (!m_empty(sm[t])) hasu |= 1u << t;
+    }
     int rounds = 0;
     while (true) {
       int32_t m1, m2, m3;
@@ -476,13 +513,20 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
         o.deferred = true;
         return o;
       }
-      uint64_t slo[N], shi[N];
+      M128 cands_all, smx;
+      if constexpr (TBL) {
+        cands_all = ltbl_get<SMALL>(row0, gmin);
+        smx = ltbl_get<SMALL>(row0, gmax);
+      } else {
+        uint64_t slo[N], shi[N];
 #pragma unroll
-      for (int t = 0; t < N; ++t) {
-        slo[t] = sm[t].lo;
-        shi[t] = sm[t].hi;
+        for (int t = 0; t < N; ++t) {
+          slo[t] = sm[t].lo;
+          shi[t] = sm[t].hi;
+        }
+        cands_all = M128{lpick(slo, gmin), lpick(shi, gmin)};
+        smx = M128{lpick(slo, gmax), lpick(shi, gmax)};
       }
-      const M128 cands_all{lpick(slo, gmin), lpick(shi, gmin)}, smx{lpick(slo, gmax), lpick(shi, gmax)};
       const int topx = m_empty(smx) ? -1 : m_top(smx);
       const uint32_t ndx = lpick(nd, gmax);
       const uint32_t ldx = lpick(load, gmax), nhx = ndx >> 25, dmx = ndx & 0x1FFFFFFu;
@@ -546,10 +590,18 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
 #pragma unroll
       for (int t = 0; t < N; ++t) {
         const bool mn = keep && t == gmin, mx = keep && t == gmax;
-        sm[t].lo = mn ? smin_new.lo : (mx ? smax_new.lo : sm[t].lo);
-        sm[t].hi = mn ? smin_new.hi : (mx ? smax_new.hi : sm[t].hi);
+        if constexpr (!TBL) {
+          sm[t].lo = mn ? smin_new.lo : (mx ? smax_new.lo : sm[t].lo);
+          sm[t].hi = mn ? smin_new.hi : (mx ? smax_new.hi : sm[t].hi);
+        }
         load[t] = mn ? ldmin : (mx ? ldx + fu : load[t]);
         K[t] = mn ? kmin1 : (mx ? kmax1 : K[t]);
+      }
+      if constexpr (TBL) {
+        if (keep) {
+          ltbl_set<SMALL>(row0, gmin, smin_new);
+          ltbl_set<SMALL>(row0, gmax, smax_new);
+        }
       }
       if (!keep) break;
       hasu |= 1u << gmax;
@@ -559,7 +611,14 @@ __device__ __forceinline__ LaneOut eval_lane(const View &V, const InstParams &P,
   // ---- path length (sec. 2.2) ----
   uint64_t cost = shsum;
 #pragma unroll
-  for (int t = 0; t < N; ++t) cost += (uint64_t)(lane_popc(hm[t]) + m_pop(sm[t])) * (uint64_t)L[t];
+  for (int t = 0; t < N; ++t) {
+    M128 st;
+    if constexpr (TBL)
+      st = embedded ? ltbl_get<SMALL>(row0, t) : M128{B.su_lo[t], SMALL ? 0ull : B.su_hi[t]};
+    else
+      st = sm[t];
+    cost += (uint64_t)(lane_popc(hm[t]) + m_pop(st)) * (uint64_t)L[t];
+  }
   o.cost = cost;
   o.makespan = tmax == kTInf ? kInfT : (tmax == kTNegInf ? kNegInfT : (int64_t)tmax);
   if (tmax == kTInf) o.flags |= kCandInfMakespan;

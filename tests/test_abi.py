@@ -49,3 +49,4 @@ def test_null_arguments_rejected_without_device():
     assert lib.bl_set_stream(None, None) == bl.EINVAL
     assert lib.bl_timing_enable(None, 1) == bl.EINVAL
     assert lib.bl_instance_upload(None, None, None) == bl.EINVAL
+    assert lib.bl_instance_info_get(None, 0, None) == bl.EINVAL

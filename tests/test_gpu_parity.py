@@ -260,6 +260,31 @@ def test_two_pass_equals_segment(ctx, name, caps):
     gg = _gpu_eval(ctx, g, words, 1 << 40)
     for x, y in zip(ga, gg):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,caps", [("mid100", (0, 0)), ("clust500", (0, 0)), ("clust500", (2, 3))])
+def test_tail_table_equals_registers(ctx, name, caps, monkeypatch):
+    """The second lane pass with every thread's SU masks in an LDS table
+    gives the outputs of the same pass with the masks in registers
+    (BL_LANE_TAIL=0 at upload), element for element, at 2^20 candidates."""
+    _say("tail table vs registers", name, caps)
+    inst = _instance(name)
+    base = _walk_base(inst, OI.init_solution(inst), 5, 40)
+    a = _setup(ctx, inst, base, 0, *caps)
+    monkeypatch.setenv("BL_LANE_TAIL", "0")
+    r = _setup(ctx, inst, base, 0, *caps)
+    monkeypatch.delenv("BL_LANE_TAIL")
+    ia, ir = ctx.instance_info(a), ctx.instance_info(r)
+    assert ia["lane_eval"] == 1 and ia["tail_table"] == 1 and ir["tail_table"] == 0
+    assert ia["wg_per_cu"] == ir["wg_per_cu"]
+    n = 1 << 20
+    d_mv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.generate(a, 93, 2, 0, 0, n, d_mv)
+    words = d_mv.cpu().numpy().view(np.uint64)
+    ga = _gpu_eval(ctx, a, words, 1 << 40)
+    gr = _gpu_eval(ctx, r, words, 1 << 40)
+    for x, y in zip(ga, gr):
+        assert np.array_equal(x, y)
     assert (ga[0] != bl.INF_KEY).any()
     if caps[1]:
         assert (ga[3] & bl.CAND_CAP_SU).any()
