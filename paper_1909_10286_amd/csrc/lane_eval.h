@@ -142,7 +142,8 @@ __device__ __forceinline__ void lane_base_fill(LaneBase &B, const View &V, const
 
 // The value in a VGPR as far as the optimiser knows, so that a select
 // chain over the tours stays a chain of selects instead of becoming an
-// indexed load from a stack copy of the array.
+// indexed load from a stack copy of the array.  lpick applies it to each
+// step's result, which dies at once, so that it costs no register copy.
 template <class T>
 __device__ __forceinline__ T lopaque(T x) {
   __asm__ volatile("" : "+v"(x));
@@ -151,12 +152,9 @@ __device__ __forceinline__ T lopaque(T x) {
 
 template <int N, class T>
 __device__ __forceinline__ T lpick(const T (&a)[N], int i) {
-  T r = lopaque(a[0]);
+  T r = a[0];
 #pragma unroll
-  for (int k = 1; k < N; ++k) {
-    const T ak = lopaque(a[k]);  // outside the select: no branch around it
-    r = i == k ? ak : r;
-  }
+  for (int k = 1; k < N; ++k) r = lopaque(i == k ? a[k] : r);
   return r;
 }
 
