@@ -181,7 +181,7 @@ int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small, bool fea
 // most max_nt tours (4, 8 or 12), 0 beyond 12.
 int batch_lane_tours(int max_nt);
 hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s);
-hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s);
+hipError_t launch_batch_prepare(const BatchParams &B, size_t lds, hipStream_t s);
 hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStream_t s);
 hipError_t launch_batch_commit(const BatchParams &B, size_t lds, hipStream_t s);
 

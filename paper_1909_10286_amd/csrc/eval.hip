@@ -345,9 +345,15 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v) { *p = v; }
 // Base preparation: optional eq. (6) pick (copy x* or x_old to the base
 // slot), then the base view written into the instance image.  Run by one
 // whole workgroup.
+// The base view is built in LDS (`limg`, the image's size) from the
+// static part staged there, and copied to the image in one coalesced pass
+// at the end; sums over a BP's or a tour's positions are LDS integer
+// atomics, one per position, so the result does not depend on their order.
 __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint64_t eps_thr,
-                             uint32_t inst_index, int &s_src) {
+                             uint32_t inst_index, int &s_src, uint32_t *limg) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const ImageLayout &L = P.lay;
+  for (uint32_t i = tid; i < L.static_words; i += nt) limg[i] = P.image[i];
   if (mode == kPrepSearch) {
     if (tid == 0) {
       const U4 w = philox4x32(U4{0u, P.st->it, inst_index, 1u}, (uint32_t)seed,
@@ -368,52 +374,53 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     __syncthreads();
   }
   const DevSol &x = P.sol[0];
-  uint32_t *img = P.image;
-  const ImageLayout &L = P.lay;
+  uint32_t *img = limg;
   uint16_t *seq = (uint16_t *)(img + L.seq), *pos = (uint16_t *)(img + L.pos);
   uint16_t *fbp = (uint16_t *)(img + L.fbp), *fidx = (uint16_t *)(img + L.fidx);
   uint16_t *bp_start = (uint16_t *)(img + L.bp_start), *bp_len = (uint16_t *)(img + L.bp_len);
   uint16_t *bp_tour = (uint16_t *)(img + L.bp_tour), *bp_idx = (uint16_t *)(img + L.bp_idx);
   uint16_t *tour_off = (uint16_t *)(img + L.tour_off), *tour_bp = (uint16_t *)(img + L.tour_bp);
+  uint16_t *t_start = (uint16_t *)(img + L.t_start), *t_end = (uint16_t *)(img + L.t_end);
   uint4 *prec = (uint4 *)(img + L.prec);
   uint32_t *w_q = img + L.w_q;
   const uint32_t *f_area = img + L.area, *f_supply = img + L.supply, *f_nsh = img + L.nsh;
   const uint32_t *f_dhq = img + L.dhq, *demand = img + L.demand;
-  uint64_t *hu_mask = (uint64_t *)(img + L.hu_mask), *su_mask = (uint64_t *)(img + L.su_mask);
   const uint16_t *hu_rank = (const uint16_t *)(img + L.hu_rank);
   const uint16_t *su_rank = (const uint16_t *)(img + L.su_rank);
+  uint32_t *b_sd = img + L.b_sd, *b_sup = img + L.b_sup, *b_area = img + L.b_area;
+  uint32_t *b_int = img + L.b_int;
+  unsigned long long *b_sh = (unsigned long long *)(img + L.b_sh);
+  uint32_t *t_len = img + L.t_len, *t_area = img + L.t_area, *t_msum = img + L.t_msum;
+  uint32_t *t_mcnt = img + L.t_mcnt;
+  uint64_t *t_sh = (uint64_t *)(img + L.t_sh);
+  unsigned long long *hu_mask = (unsigned long long *)(img + L.hu_mask);
+  unsigned long long *su_mask = (unsigned long long *)(img + L.su_mask);
 
-  // LDS copies of the tour lists and BP lengths for the serial prefix below
-  // (its reads then wait on LDS, not on global memory).
-  __shared__ uint16_t s_toff[kMaxTours + 1], s_tbp[kMaxBps], s_blen[kMaxBps];
-  for (int i = tid; i <= P.NT; i += nt) {
-    const uint16_t v = x.tour_off[i];
-    tour_off[i] = v;
-    s_toff[i] = v;
-  }
+  // The base view's words start at zero (the sums and masks below add into them).
+  for (uint32_t i = L.static_words + tid; i < L.total_words; i += nt) img[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i <= P.NT; i += nt) tour_off[i] = x.tour_off[i];
+  // The BP of each slot of the id-ordered field lists, kept for now in the
+  // skip legs' words (written only after it is last read).
+  uint32_t *owner = img + L.skip;
   for (int i = tid; i < P.NB; i += nt) {
-    const uint16_t v = x.tour_bp[i];
-    tour_bp[i] = v;
-    s_tbp[i] = v;
-  }
-  for (int i = tid; i < P.NB; i += nt) {
-    const uint16_t v = (uint16_t)(x.bp_off[i + 1] - x.bp_off[i]);
-    bp_len[i] = v;
-    s_blen[i] = v;
+    tour_bp[i] = x.tour_bp[i];
+    const int o0 = x.bp_off[i], o1 = x.bp_off[i + 1];
+    bp_len[i] = (uint16_t)(o1 - o0);
+    for (int j = o0; j < o1; ++j) owner[j] = (uint32_t)i;
   }
   __syncthreads();
-  uint16_t *t_start = (uint16_t *)(img + L.t_start), *t_end = (uint16_t *)(img + L.t_end);
   if (tid == 0) {
     // BP start positions in tour order (serial prefix over the BPs).
     uint32_t run = 0;
     for (int g = 0; g < P.NT; ++g) {
       t_start[g] = (uint16_t)run;
-      for (int j = s_toff[g]; j < s_toff[g + 1]; ++j) {
-        const int b = s_tbp[j];
+      for (int j = tour_off[g]; j < tour_off[g + 1]; ++j) {
+        const int b = tour_bp[j];
         bp_tour[b] = (uint16_t)g;
-        bp_idx[b] = (uint16_t)(j - s_toff[g]);
+        bp_idx[b] = (uint16_t)(j - tour_off[g]);
         bp_start[b] = (uint16_t)run;
-        run += s_blen[b];
+        run += bp_len[b];
       }
       t_end[g] = (uint16_t)run;
     }
@@ -426,13 +433,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
   __syncthreads();
   const uint32_t nb1 = 1u + (uint32_t)P.NB;
   for (int i = tid; i < P.NF; i += nt) {
-    // BP owning slot i of the id-ordered field lists (upper bound search).
-    int lo = 0, hi = P.NB;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if ((int)x.bp_off[mid] <= i) lo = mid; else hi = mid;
-    }
-    const int b = lo;
+    const int b = (int)owner[i];
     const int k = i - x.bp_off[b];
     const int f = x.bp_field[i];
     const int q = bp_start[b] + k;
@@ -447,31 +448,28 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     w_q[q] = 2u * f_nsh[f] * d;
   }
   __syncthreads();
+  // Per position: the leg into it, the leg that closes the route when its
+  // field leaves, and its share of its BP's and tour's sums (every sum is
+  // the one the full walk forms, over the same fields).
   for (int q = tid; q < P.NF; q += nt) {
+    const int f = seq[q], b = fbp[f], g = bp_tour[b];
     const uint32_t a = q == 0 ? 0u : nb1 + seq[q - 1];
-    prec[q].x = P.dist[(size_t)a * P.V + nb1 + seq[q]];
+    const uint32_t leg = P.dist[(size_t)a * P.V + nb1 + f];
+    prec[q].x = leg;
+    const int po = q > (int)t_start[g] ? seq[q - 1] : -1, no = q + 1 < (int)t_end[g] ? seq[q + 1] : -1;
+    img[L.skip + q] = po < 0 ? (no < 0 ? 0u : f_dhq[no])
+                             : (no < 0 ? f_dhq[po] : P.dist[(size_t)(nb1 + po) * P.V + nb1 + no]);
+    const uint4 r = prec[q];
+    atomicAdd(&b_sd[b], r.y);
+    atomicAdd(&b_area[b], r.z);
+    atomicAdd(&b_sup[b], r.w);
+    atomicAdd(&b_sh[b], (unsigned long long)w_q[q]);
+    if (q > (int)bp_start[b]) atomicAdd(&b_int[b], leg);
+    if (q > (int)t_start[g]) atomicAdd(&t_len[g], leg);
   }
   __syncthreads();
-  // Base aggregates per BP, then per tour (every sum is the one the full walk
-  // forms, over the same fields).
-  uint32_t *b_sd = img + L.b_sd, *b_sup = img + L.b_sup, *b_area = img + L.b_area;
-  uint32_t *b_int = img + L.b_int;
-  uint64_t *b_sh = (uint64_t *)(img + L.b_sh);
   for (int b = tid; b < P.NB; b += nt) {
-    uint32_t sd = 0, sup = 0, ar = 0, in = 0;
-    uint64_t sh = 0;
-#pragma unroll 8
-    for (int q = bp_start[b]; q < bp_start[b] + bp_len[b]; ++q) {
-      const uint4 r = prec[q];
-      sd += r.y;
-      ar += r.z;
-      sup += r.w;
-      sh += w_q[q];
-      if (q > bp_start[b]) in += r.x;
-    }
-    b_int[b] = in;
-    b_sd[b] = sd;
-    img[L.b_mean + b] = bp_len[b] ? sd / bp_len[b] : 0u;
+    img[L.b_mean + b] = bp_len[b] ? b_sd[b] / bp_len[b] : 0u;
     // The leg that closes the route when the BP's fields leave it.
     uint32_t bridge = 0;
     if (bp_len[b]) {
@@ -481,26 +479,12 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
                       : (no < 0 ? f_dhq[po] : P.dist[(size_t)(nb1 + po) * P.V + nb1 + no]);
     }
     img[L.b_skip + b] = bridge;
-    b_sup[b] = sup;
-    b_area[b] = ar;
-    b_sh[b] = sh;
   }
-  // The leg that closes the route when the field at position q leaves it.
-  for (int q = tid; q < P.NF; q += nt) {
-    const int g = bp_tour[fbp[seq[q]]];
-    const int po = q > (int)t_start[g] ? seq[q - 1] : -1, no = q + 1 < (int)t_end[g] ? seq[q + 1] : -1;
-    img[L.skip + q] = po < 0 ? (no < 0 ? 0u : f_dhq[no])
-                             : (no < 0 ? f_dhq[po] : P.dist[(size_t)(nb1 + po) * P.V + nb1 + no]);
-  }
-  __syncthreads();
-  uint32_t *t_len = img + L.t_len, *t_area = img + L.t_area, *t_msum = img + L.t_msum;
-  uint32_t *t_mcnt = img + L.t_mcnt;
-  uint64_t *t_sh = (uint64_t *)(img + L.t_sh);
   for (int g = tid; g < P.NT; g += nt) {
-    uint32_t len = 0, ar = 0, ms = 0, mc = 0;
+    uint32_t ar = 0, ms = 0, mc = 0;
     uint64_t sh = 0;
-    for (int j = x.tour_off[g]; j < x.tour_off[g + 1]; ++j) {
-      const int b = x.tour_bp[j];
+    for (int j = tour_off[g]; j < tour_off[g + 1]; ++j) {
+      const int b = tour_bp[j];
       ar += b_area[b];
       sh += b_sh[b];
       if (bp_len[b]) {
@@ -509,12 +493,9 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
       }
     }
     const int q0 = t_start[g], q1 = t_end[g];
-    if (q1 > q0) {
-      len = f_dhq[seq[q0]] + f_dhq[seq[q1 - 1]];
-#pragma unroll 8
-      for (int q = q0 + 1; q < q1; ++q) len += prec[q].x;
-    }
-    t_len[g] = len;
+    // The legs between the tour's fields are summed above; the two legs to
+    // and from HQ close the route.
+    if (q1 > q0) t_len[g] += f_dhq[seq[q0]] + f_dhq[seq[q1 - 1]];
     t_area[g] = ar;
     t_sh[g] = sh;
     t_msum[g] = ms;
@@ -525,31 +506,21 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
     for (int b = 0; b < P.NB; ++b) v += b_sup[b] < demand[b] ? 1u : 0u;
     img[L.n_viol] = v;
   }
-  // Unit masks per tour: one thread per unit sets its rank bit (bitwise OR
-  // in LDS, so the order does not matter).
-  __shared__ unsigned long long s_hm[kMaxTours], s_sm[2 * kMaxTours];
-  for (int g = tid; g < P.NT; g += nt) {
-    s_hm[g] = 0ull;
-    s_sm[2 * g] = s_sm[2 * g + 1] = 0ull;
-  }
-  __syncthreads();
-  for (int h = tid; h < P.NHU; h += nt) atomicOr(&s_hm[x.hu_tour[h]], 1ull << hu_rank[h]);
+  // Unit masks per tour: one thread per unit sets its rank bit (bitwise OR,
+  // so the order does not matter).
+  for (int h = tid; h < P.NHU; h += nt) atomicOr(&hu_mask[x.hu_tour[h]], 1ull << hu_rank[h]);
   for (int u = tid; u < P.NSU; u += nt) {
     const int r = su_rank[u];
-    atomicOr(&s_sm[2 * x.su_tour[u] + (r >> 6)], 1ull << (r & 63));
+    atomicOr(&su_mask[2 * x.su_tour[u] + (r >> 6)], 1ull << (r & 63));
   }
   __syncthreads();
-  for (int g = tid; g < P.NT; g += nt) {
-    hu_mask[g] = s_hm[g];
-    su_mask[2 * g] = s_sm[2 * g];
-    su_mask[2 * g + 1] = s_sm[2 * g + 1];
-  }
+  for (uint32_t i = L.static_words + tid; i < L.total_words; i += nt) P.image[i] = img[i];
 }
 
 __global__ __launch_bounds__(1024) void k_prepare(InstParams P, int mode, uint64_t seed,
                                                   uint64_t eps_thr, uint32_t inst_index) {
   __shared__ int s_src;
-  prepare_body(P, mode, seed, eps_thr, inst_index, s_src);
+  prepare_body(P, mode, seed, eps_thr, inst_index, s_src, reinterpret_cast<uint32_t *>(g_lds4));
 }
 
 // Moves for candidates first..first+n-1 (one thread each), read from the
@@ -755,7 +726,7 @@ __global__ void k_batch_reset(uint32_t *queue) {
 __global__ __launch_bounds__(256) void k_prepare_multi(BatchParams B, int mode) {
   __shared__ int s_src;
   const uint32_t k = blockIdx.x;
-  prepare_body(B.inst[k], mode, B.seed, B.eps_thr, B.index_base + k, s_src);
+  prepare_body(B.inst[k], mode, B.seed, B.eps_thr, B.index_base + k, s_src, reinterpret_cast<uint32_t *>(g_lds4));
 }
 
 __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
@@ -957,7 +928,8 @@ size_t eval_lds_bytes(const InstParams &P) {
 
 hipError_t launch_prepare(const InstParams &P, int mode, uint64_t seed, uint64_t eps_thr,
                           uint32_t inst_index, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, s, P, mode, seed, eps_thr, inst_index);
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), (size_t)round4(P.lay.total_words) * 4, s, P, mode, seed, eps_thr,
+                     inst_index);
   return hipGetLastError();
 }
 
@@ -1206,7 +1178,7 @@ int batch_occupancy(size_t lds, bool walk, int lane_n, bool lane_small, bool que
 int batch_lane_tours(int max_nt) { return max_nt <= 4 ? 4 : (max_nt <= 8 ? 8 : (max_nt <= kLaneMaxTours ? 12 : 0)); }
 
 hipError_t launch_batch_start(const BatchParams &B, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare_multi, dim3(B.K), dim3(256), 0, s, B, (int)kPrepFromBase);
+  hipLaunchKernelGGL(k_prepare_multi, dim3(B.K), dim3(256), lds, s, B, (int)kPrepFromBase);
   hipLaunchKernelGGL(k_commit_multi, dim3(B.K), dim3(256), lds, s, B, (int)kCommitStart);
   return hipGetLastError();
 }
@@ -1235,8 +1207,8 @@ hipError_t launch_batch_eval(const BatchParams &B, int grid, size_t lds, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_batch_prepare(const BatchParams &B, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare_multi, dim3(B.K), dim3(256), 0, s, B, (int)kPrepSearch);
+hipError_t launch_batch_prepare(const BatchParams &B, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare_multi, dim3(B.K), dim3(256), lds, s, B, (int)kPrepSearch);
   return hipGetLastError();
 }
 

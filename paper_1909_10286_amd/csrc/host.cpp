@@ -324,7 +324,7 @@ int batch_grid(const bl_ctx *c, const Batch &B) {
 
 bl_status batch_step_on(bl_ctx *c, Batch &B, const bl_search_params *p, hipStream_t q) {
   const BatchParams bp = batch_params(B, p);
-  HIP_TRY(c, launch_batch_prepare(bp, q));
+  HIP_TRY(c, launch_batch_prepare(bp, B.lds, q));
   HIP_TRY(c, timing_mark(c));
   HIP_TRY(c, launch_batch_eval(bp, batch_grid(c, B), B.lds, q));
   HIP_TRY(c, timing_mark(c));
