@@ -38,7 +38,8 @@ __device__ __forceinline__ uint64_t udiv(uint64_t p, uint32_t q) {
   return (uint64_t)((double)p / (double)q);
 }
 
-// udiv with a 64-bit divisor: exact for p + q < 2^53, q > 0.
+// udiv with a 64-bit divisor: exact for p + q < 2^53, q > 0, and 0 for any
+// q > p (p < 2^53): the quotient then rounds to at most 1 - 2^-53.
 __device__ __forceinline__ uint64_t udiv_wide(uint64_t p, uint64_t q) {
   return (uint64_t)((double)p / (double)q);
 }
@@ -816,19 +817,30 @@ __device__ __forceinline__ EvalOut eval_candidate(const View &V, const InstParam
       // outranks it.
       const uint64_t rt_top = (nhx != 0 && topx >= 0) ? udiv(7200ull * dmx, V.su_speed[topx]) : 0ull;
       const double r_nhx = nhx ? 1.0 / (double)nhx : 0.0;
+      // The donor's units in rank order: the first whose move takes g_max's
+      // waiting time below w2, else the last (the first without g2, the last
+      // without HUs).  As in the lane version, each form of the trial is
+      // below w2 exactly when one integer of the unit passes a bound formed
+      // once per round: f_u >= nhx * (rt_top - w2 + 1) - (ldx - f_topx) for a
+      // unit ranked below the critical SU topx, v_u >= floor(7200 dmx / K) + 1
+      // with K = w2 + floor(ldx / nhx) > 0 for one ranked above it (K
+      // saturates where w2 is +inf: every finite trial is below it).
       int u = 0;
-      while (!m_empty(cands)) {
-        u = m_pop_low(cands);
-        int64_t trial;
-        if (nhx == 0) {
-          trial = kInfT;
-        } else {
-          const int s = u > topx ? u : topx;
-          const uint32_t ld = ldx + V.su_fill[u];
-          const uint64_t rt = u > topx ? udiv(7200ull * dmx, V.su_speed[u]) : rt_top;
-          trial = (int64_t)rt - (int64_t)udiv_small(ld - V.su_fill[s], nhx, r_nhx);
+      if (!has2 || nhx == 0) {
+        u = has2 ? m_top(cands) : m_pop_low(cands);
+      } else {
+        const int64_t J = (int64_t)rt_top - w2 + 1;
+        const uint32_t C = topx >= 0 ? ldx - V.su_fill[topx] : 0u;
+        const int64_t fa = J <= 0 ? 0 : (int64_t)nhx * J - (int64_t)C;
+        const uint32_t fbound = fa <= 0 ? 0u : (fa >= (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)fa);
+        const int64_t q = (int64_t)udiv_small(ldx, nhx, r_nhx);
+        const int64_t Kb = w2 > INT64_MAX - q ? INT64_MAX : w2 + q;
+        const uint64_t vbound = Kb <= 0 ? ~0ull : udiv_wide(7200ull * dmx, (uint64_t)Kb) + 1ull;
+        while (true) {
+          u = m_pop_low(cands);
+          const bool ok = u < topx ? V.su_fill[u] >= fbound : (uint64_t)V.su_speed[u] >= vbound;
+          if (ok || m_empty(cands)) break;
         }
-        if (!has2 || trial < w2 || m_empty(cands)) break;
       }
       const uint32_t fu = V.su_fill[u];
       if (t == gmin) { m_clear(sm, u); load -= fu; }

@@ -45,9 +45,17 @@ def _gpu_eval(ctx, iid, words, t_star):
             d_mk.cpu().numpy()[:n], d_fl.cpu().numpy()[:n])
 
 
+# Instances past the one-candidate-per-lane limit of 12 tours: the segment
+# version at its widths of 32 and 64 lanes (17-32 and 33-64 tours).
+_WIDE = {"tours20": (200, 30, 20, 40, 80), "tours40": (240, 48, 40, 64, 120)}
+
+
 def _instance(name, seed=0):
     if name.startswith("batch"):
         return inputs.make_batch_instance(int(name[5:]), accept=OI.init_feasible)
+    if name in _WIDE:
+        nf, nb, nt, nh, ns = _WIDE[name]
+        return inputs.make_custom_instance(name, seed, 100_000, nf, nb, nt, nh, ns, accept=OI.init_feasible)
     return inputs.make_instance(name, seed, accept=OI.init_feasible)
 
 
@@ -162,6 +170,11 @@ CASES = [
     # The segment version (one tour per lane) where one lane per candidate is the default.
     ("mid100", 2085, "walk", bl.SEGMENT_EVAL, (0, 0), "big"),
     ("tiny12", 1000, "inactive", bl.SEGMENT_EVAL, (0, 0), "base"),
+    # More than 12 tours: segments of 32 and 64 lanes, 64-bit keys.
+    ("tours20", 600, "walk", 0, (0, 0), "big"),
+    ("tours20", 600, "init", 0, (0, 0), "base"),
+    ("tours40", 400, "walk", 0, (0, 0), "big"),
+    ("tours40", 400, "init", bl.FULL_WALK, (2, 3), "base"),
 ]
 
 
