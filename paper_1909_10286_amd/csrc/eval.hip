@@ -84,15 +84,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // The same launch with one candidate per lane (lane_eval.h): for instances of
 // at most kLaneMaxTours tours, unless a flag asks for the segment version.
-// phase 0: candidates 0 .. n-1; one whose SU rounds go past su_defer_rounds(N)
+// phase 0: candidates 0 .. n-1; one whose SU rounds go past kSuDeferRounds
 // rounds is appended to the instance's deferred list (while it has room)
 // instead of holding its wave in a long tail of rounds.  phase 1: the
 // deferred candidates, densely, with no limit.  A deferred candidate is
 // evaluated again from the start, so the limit trades that repeated work
-// against the tail; rounds cost more with more tours, and the tails grow
-// longer.  Measured: 3 rounds is fastest at 5 tours (of 1, 2, 3), 1 round at
-// 10 tours.
-constexpr int su_defer_rounds(int n_tours) { return n_tours <= 6 ? 3 : 1; }
+// against the tail.  Measured: one round is fastest at 5 and at 10 tours (of
+// 1, 2, 3) now that the second pass keeps its SU masks in LDS; with that pass
+// in registers, 3 rounds had been fastest at 5 tours.
+constexpr int kSuDeferRounds = 1;
 
 // The deferred list holds two classes, each in a part of its own with a
 // count of its own: BP moves (class 0) and field moves (class 1).  A BP move
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
     it = P.st->it;
     t_star = P.st->t_best;
   }
-  const int su_limit = phase == 0 && P.defer_cap ? su_defer_rounds(N) : 0;
+  const int su_limit = phase == 0 && P.defer_cap ? kSuDeferRounds : 0;
   uint64_t best = kInfKey;
   // Full evaluation of feasible candidate c (move word w), from round limit
   // lim0.  A candidate whose SU rounds pass the limit goes to the
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
 // members all have at most N tours and 32-bit time bounds: a member's tours
 // beyond its own count are empty and inactive (eval_lane's nt), so one
 // instantiation serves members of any smaller tour count.  A candidate whose
-// SU rounds run past su_defer_rounds(N_T) is queued in LDS (up to
+// SU rounds run past kSuDeferRounds is queued in LDS (up to
 // kLocalDefer per item) and evaluated again, densely, once the item's other
 // candidates are done.
 constexpr uint32_t kLocalDefer = 1024;
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(256, QUEUE ? kLaneWaves : 1) void k_eval_multi_lane
     const int64_t t_star = P.st->t_best;
     const uint32_t idx = B.index_base + k;
     const int nt = P.NT;
-    const int su_limit = su_defer_rounds(nt);
+    const int su_limit = kSuDeferRounds;
     uint64_t best = kInfKey;
     // A candidate whose SU rounds pass su_limit goes to the work item's tail
     // queue (or, when that is full, is finished here).  Without QUEUE each

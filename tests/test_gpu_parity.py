@@ -253,13 +253,13 @@ def test_deferred_list_overflow(ctx, name):
 
 
 @pytest.mark.parametrize("name,caps", [("mid100", (0, 0)), ("clust500", (0, 0)),
-                                       ("mid100", (0, 4)), ("clust500", (2, 3))])
+                                       ("mid100", (0, 3)), ("clust500", (2, 3))])
 def test_two_pass_equals_segment(ctx, name, caps):
     """At 2^20 candidates the lane evaluation runs its two passes (long SU
     tails deferred to the second); its outputs equal the segment version's
     (one pass, one tour per lane) element for element, also where the SU cap
-    (4 at 5 tours, 3 at 10) lies just past the deferral limit (3 and 1
-    rounds), so that deferred candidates hit it in the second pass."""
+    (3 rounds) lies just past the deferral limit (1 round), so that deferred
+    candidates hit it in the second pass."""
     _say("two passes vs segment", name, caps)
     inst = _instance(name)
     base = _walk_base(inst, OI.init_solution(inst), 5, 40)
