@@ -275,6 +275,19 @@ def test_two_pass_equals_segment(ctx, name, caps):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("name,flags,lane,table", [("mid100", 0, 1, 1), ("clust500", 0, 1, 1),
+                                                   ("clust500", bl.SEGMENT_EVAL, 0, 0), ("tours40", 0, 0, 0)])
+def test_instance_info_names_the_kernels(ctx, name, flags, lane, table):
+    """bl_instance_info_get reports one candidate per lane up to 12 tours
+    (with the LDS-table second pass where it keeps the workgroups per CU),
+    the segment version beyond or on request, and the image size."""
+    _say("instance info", name, flags)
+    inst = _instance(name)
+    info = ctx.instance_info(ctx.instance_upload(inst, flags=flags))
+    assert (info["lane_eval"], info["tail_table"]) == (lane, table)
+    assert info["wg_per_cu"] >= 1 and info["image_bytes"] > 22 * inst.n_fields
+
+
 @pytest.mark.parametrize("name,caps", [("mid100", (0, 0)), ("clust500", (0, 0)), ("clust500", (2, 3))])
 def test_tail_table_equals_registers(ctx, name, caps, monkeypatch):
     """The second lane pass with every thread's SU masks in an LDS table
