@@ -99,6 +99,18 @@ struct TraceRow {
   uint8_t indicator, use_best, pad[2];
 };
 
+// The minimised units of the candidate that held the best key when the
+// second lane pass started (usually the iteration's winner), formed by one
+// extra workgroup of that pass while the others run; the commit takes them
+// instead of evaluating the winner again when the key and iteration match.
+constexpr int kRecTours = 12;
+struct WinRec {
+  uint64_t key, cost;
+  int64_t makespan;
+  uint32_t it, valid;
+  uint64_t hm[kRecTours], su_lo[kRecTours], su_hi[kRecTours];
+};
+
 // Everything a kernel needs to know about one instance (passed by value).
 struct InstParams {
   int32_t NF, NB, NT, NHU, NSU, V;
@@ -120,6 +132,7 @@ struct InstParams {
   uint32_t defer_cap;  // entries per class; 0: no deferral
   uint32_t defer_zeroed; // host side: the base preparation of this iteration already cleared the count
   int32_t lane_tail;   // host side: the second lane pass keeps the SU masks in LDS (k_eval_lane_tail)
+  WinRec *rec;         // the winner's units formed during the second pass (search and gather launches); null: none
   uint16_t *hu_id;     // rank -> HU id
   uint16_t *su_id;     // rank -> SU id
 };

@@ -293,6 +293,46 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane(InstParams P, int
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
 }
 
+// Evaluates the candidate that holds the instance's best key (the first
+// pass's best, or a better one the second pass already found) with the
+// segment version, as the commit would, and keeps its minimised units in
+// P.rec with its key and iteration.  Run by one workgroup of the second
+// pass; the commit uses the record only where its key is the iteration's
+// final best.
+// `staged`: the image is already in LDS.
+__device__ void winner_units(const InstParams &P, uint64_t seed, uint32_t inst_index, bool staged) {
+  __shared__ uint64_t s_key;
+  if (threadIdx.x == 0) s_key = *(volatile uint64_t *)P.best_key;
+  uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
+  if (!staged) stage(lds, P.image, P.lay.total_words);
+  __syncthreads();
+  const uint64_t key = s_key;
+  if (key == kInfKey || threadIdx.x >= 64) return;
+  const View V = make_view(lds, P.lay, P.dist);
+  const uint32_t it = P.st->it;
+  const Move m = decode_move(draw_move(seed, (uint32_t)(key & 0xFFFFFFu), it, inst_index, V, P), V, P);
+  const int S = P.seg;
+  const int t = threadIdx.x & (S - 1);
+  const uint64_t seg_mask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
+  const int seg_base = threadIdx.x & ~(S - 1);
+  if (seg_base != 0) return;
+  const EvalOut o = eval_candidate<false, 0>(V, P, m, t, S, seg_base, seg_mask);
+  WinRec &w = *P.rec;
+  if (t < P.NT && t < kRecTours) {
+    w.hm[t] = o.hu_mask;
+    w.su_lo[t] = o.su_mask.lo;
+    w.su_hi[t] = o.su_mask.hi;
+  }
+  if (t == 0) {
+    w.key = key;
+    w.cost = o.cost;
+    w.makespan = o.makespan;
+    w.it = it;
+  }
+  __threadfence();
+  if (t == 0) w.valid = 1u;
+}
+
 // The second pass over the deferred list where the SU masks of every thread
 // fit in LDS beside the image (rows of N entries after it, ltbl_get): a
 // round then reads and writes the two tours' masks in LDS instead of
@@ -308,10 +348,18 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane_tail(InstParams P
                                                         const uint32_t *__restrict__ gather,
                                                         const uint32_t *__restrict__ run_flag) {
   if (run_flag && *run_flag == 0u) return;
+  // In search and gather launches the last workgroup also forms the units of
+  // the best candidate so far, after its own candidates: they are the last
+  // field moves of the list (short tails), so it is done long before the
+  // waves of long BP tails are.
+  const bool extra = MODE != kModeBatch && P.rec && blockIdx.x == gridDim.x - 1;
   const uint32_t cap = P.defer_cap;
   const uint32_t n_bp = min(P.defer_cnt[0], cap);
   const uint32_t total = n_bp + min(P.defer_cnt[1], cap);
-  if (blockIdx.x * blockDim.x >= total) return;
+  if (blockIdx.x * blockDim.x >= total) {
+    if (extra) winner_units(P, seed, inst_index, false);
+    return;
+  }
   __shared__ LaneBase s_base;
   uint32_t *lds = reinterpret_cast<uint32_t *>(g_lds4);
   stage(lds, P.image, P.lay.total_words);
@@ -338,6 +386,10 @@ __global__ __launch_bounds__(256, kLaneWaves) void k_eval_lane_tail(InstParams P
     best = r.key < best ? r.key : best;
   }
   if (MODE != kModeBatch) wave_min_to(best, P.best_key);
+  if (extra) {
+    __syncthreads();
+    winner_units(P, seed, inst_index, true);
+  }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v) { *p = v; }
@@ -552,8 +604,10 @@ __global__ void k_select(const uint64_t *__restrict__ keys, uint32_t n, uint64_t
 // a no-op move and the gate off becomes x* and x_old.  Step mode: the winner
 // of the iteration is rebuilt from its draw, x_old <- x_new, and x* <- x_new
 // on a strict decrease of C; one trace row.
+// use_rec: the winner's units may come from the second lane pass's record
+// (single-instance search and gather launches).
 __device__ void commit_body(const InstParams &P, const View &V, int mode, uint64_t seed,
-                            uint32_t inst_index) {
+                            uint32_t inst_index, bool use_rec) {
   __shared__ uint64_t s_mv;
   __shared__ int s_win, s_improved;
   __shared__ uint64_t s_cost;
@@ -604,8 +658,24 @@ __device__ void commit_body(const InstParams &P, const View &V, int mode, uint64
     return;
   }
   const Move m = decode_move(s_mv, V, P);
-  // Wave 0 evaluates the winner and writes its minimised units.
-  if (tid < 64) {
+  // The winner's units from the second pass's record where it holds this
+  // iteration's winner; else wave 0 evaluates the winner and writes them.
+  const bool from_rec = use_rec && mode == kCommitStep && P.rec && P.rec->valid && P.rec->key == bkey &&
+                        P.rec->it == it;
+  if (from_rec) {
+    const WinRec &w = *P.rec;
+    for (int t = tid; t < P.NT; t += nt) {
+      for (uint64_t mm = w.hm[t]; mm; mm &= mm - 1)
+        xo.hu_tour[P.hu_id[__ffsll((unsigned long long)mm) - 1]] = (uint16_t)t;
+      M128 sm{w.su_lo[t], w.su_hi[t]};
+      while (!m_empty(sm)) xo.su_tour[P.su_id[m_pop_low(sm)]] = (uint16_t)t;
+    }
+    if (tid == 0) {
+      s_cost = w.cost;
+      s_mk = w.makespan;
+    }
+  } else if (tid < 64) {
+    // Wave 0 evaluates the winner and writes its minimised units.
     const int S = P.seg;
     const int t = tid & (S - 1);
     const uint64_t seg_mask = S == 64 ? ~0ull : ((1ull << S) - 1ull);
@@ -710,7 +780,7 @@ __global__ __launch_bounds__(256) void k_commit(InstParams P, int mode, uint64_t
   if (DLDS) stage(lds + img_words, P.dist, (uint32_t)(P.V * P.V));
   __syncthreads();
   const View V = make_view(lds, P.lay, DLDS ? lds + img_words : P.dist);
-  commit_body(P, V, mode, seed, inst_index);
+  commit_body(P, V, mode, seed, inst_index, true);
 }
 
 // ------------------------------------------------- batches of instances --
@@ -736,7 +806,7 @@ __global__ __launch_bounds__(256) void k_commit_multi(BatchParams B, int mode) {
   stage(lds, P.image, P.lay.total_words);
   __syncthreads();
   const View V = make_view(lds, P.lay, P.dist);
-  commit_body(P, V, mode, B.seed, B.index_base + k);
+  commit_body(P, V, mode, B.seed, B.index_base + k, false);
 }
 
 // The batched evaluation with one candidate per lane, for batches whose

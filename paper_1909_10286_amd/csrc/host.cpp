@@ -42,6 +42,7 @@ struct Instance {
   TraceRow *d_trace = nullptr;
   uint64_t *d_best = nullptr;   // argmin slot (8 B), then the deferred-candidate counts (2 x 4 B)
   uint32_t *d_defer = nullptr;  // deferred-candidate list of the one-candidate-per-lane launches (2 classes)
+  WinRec *d_rec = nullptr;      // the winner's units formed during their second pass
   bool base_ready = false, started = false;
   int occ_batch = 1, occ_search = 1;
 };
@@ -156,6 +157,7 @@ void free_instance(Instance *I) {
   (void)hipFree(I->d_trace);
   (void)hipFree(I->d_best);
   (void)hipFree(I->d_defer);
+  (void)hipFree(I->d_rec);
 }
 
 // Solution slot layout inside one u16 buffer.
@@ -720,6 +722,13 @@ bl_status bl_instance_upload(bl_ctx *c, const bl_instance *in, int32_t *inst_id)
   R->occ_batch = eval_occupancy(P, false);
   R->occ_search = eval_occupancy(P, true);
   P.lane_tail = lane_tail_on(P) ? 1 : 0;
+  P.rec = nullptr;
+  if (P.lane_tail) {
+    if ((e = hipMalloc(&R->d_rec, sizeof(WinRec))) != hipSuccess ||
+        (e = hipMemset(R->d_rec, 0, sizeof(WinRec))) != hipSuccess)
+      return cleanup(hip_fail(c, e, "hipMalloc winner record"));
+    P.rec = R->d_rec;
+  }
   c->inst.push_back(std::move(I));
   *inst_id = (int32_t)c->inst.size() - 1;
   return BL_OK;
