@@ -288,6 +288,37 @@ def test_instance_info_names_the_kernels(ctx, name, flags, lane, table):
     assert info["wg_per_cu"] >= 1 and info["image_bytes"] > 22 * inst.n_fields
 
 
+@pytest.mark.parametrize("name,iters", [("mid100", 6), ("clust500", 3)])
+def test_winner_record_equals_reevaluation(ctx, name, iters, monkeypatch):
+    """Searches at full candidate counts (two lane passes): where the second
+    pass forms the winner's units for the commit (default upload), the
+    trajectory, trace and solutions equal those of the same search whose
+    commit evaluates the winner again (BL_LANE_TAIL=0 at upload: no record)."""
+    _say("winner record vs re-evaluation", name)
+    inst = _instance(name)
+    x0 = to_csr(OI.init_solution(inst))
+    n = inputs.WORKLOADS[name]["n_cand"]
+    out = []
+    for tail in (None, "0"):
+        if tail is None:
+            monkeypatch.delenv("BL_LANE_TAIL", raising=False)
+        else:
+            monkeypatch.setenv("BL_LANE_TAIL", tail)
+        iid = ctx.instance_upload(inst)
+        monkeypatch.delenv("BL_LANE_TAIL", raising=False)
+        assert ctx.instance_info(iid)["tail_table"] == (1 if tail is None else 0)
+        ctx.solution_upload(iid, bl.SLOT_BASE, x0)
+        ctx.search_start(iid, iters)
+        for _ in range(iters):
+            ctx.search_step(iid, 17, 1 << 31, n)
+        out.append((ctx.search_state(iid), ctx.search_trace(iid),
+                    from_csr(ctx.solution_download(iid, bl.SLOT_OLD)),
+                    from_csr(ctx.solution_download(iid, bl.SLOT_BEST))))
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    assert out[0][2] == out[1][2] and out[0][3] == out[1][3]
+
+
 @pytest.mark.parametrize("name,caps", [("mid100", (0, 0)), ("clust500", (0, 0)), ("clust500", (2, 3))])
 def test_tail_table_equals_registers(ctx, name, caps, monkeypatch):
     """The second lane pass with every thread's SU masks in an LDS table
