@@ -99,10 +99,12 @@ struct TraceRow {
   uint8_t indicator, use_best, pad[2];
 };
 
-// The minimised units of the candidate that held the best key when the
-// second lane pass started (usually the iteration's winner), formed by one
-// extra workgroup of that pass while the others run; the commit takes them
-// instead of evaluating the winner again when the key and iteration match.
+// The minimised units of the candidate that held the best key when the last
+// workgroup of the second lane pass finished its own candidates (usually the
+// iteration's winner), formed by that workgroup while the others run; the
+// commit takes them instead of evaluating the winner again when the record
+// is valid (the base preparation clears it each iteration) and its key and
+// iteration match.
 constexpr int kRecTours = 12;
 struct WinRec {
   uint64_t key, cost;

@@ -481,6 +481,7 @@ __device__ void prepare_body(const InstParams &P, int mode, uint64_t seed, uint6
       P.defer_cnt[0] = 0u;
       P.defer_cnt[1] = 0u;
     }
+    if (P.rec) P.rec->valid = 0u;   // only this iteration's second pass may form the winner's units
   }
   __syncthreads();
   const uint32_t nb1 = 1u + (uint32_t)P.NB;
